@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for the compact FAM scheme with single-step OE.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product path (the
+HIP library and its Python binding) never imports, links or calls it, and this
+package imports nothing from the product.
+
+The oracle is plain, slow and written from the paper's definitions:
+
+* ``oracle.exact``   - the reconstruction operators, obtained by solving the
+                       moment-matching systems of Sec. 2.4 in exact rational
+                       arithmetic and projecting in L2 (not from printed tables);
+* ``oracle.physics`` - fluxes, wave speeds, Rusanov flux, 4-point Gauss rule;
+* ``oracle.scheme``  - ghost cells, R(U) (eqs. 1dSemi, 11), SSP-RK3 (eqs. 3, 12),
+                       OE (Prop. 2.1, eqs. 1dOE_system, 2dOE_system, Tables
+                       sigma1d / sigma2d), CFL time step (Sec. 4);
+* ``oracle.functional`` - the final-time functional used by the adjoint and its
+                       reference gradient by reverse-mode differentiation of the
+                       oracle's own step.
+
+All floating-point work is FP64 (torch CPU tensors).  Where the paper is silent
+or ambiguous the oracle takes one documented reading (wave speed of the Rusanov
+flux evaluated pointwise from both traces; transmissive ghosts copy every
+moment; the k = 6 two-dimensional OE jumps use p_6 by default).
+"""
+from .physics import NonPhysicalState, gauss4  # noqa: F401
+from .scheme import Config, cfl_dt, oe, residual, rk3, rk3_stage, run, step  # noqa: F401

@@ -1,0 +1,105 @@
+"""Parsers for the printed-table fixtures under tests/golden (exact rationals)."""
+import os
+import re
+from fractions import Fraction as Fr
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+class Lin:
+    """A linear form with Fraction coefficients over symbolic moments."""
+
+    def __init__(self, terms=None):
+        self.t = dict(terms or {})
+
+    def _coerce(self, o):
+        return o if isinstance(o, Lin) else Lin({(): Fr(o)}) if o != 0 else Lin()
+
+    def __add__(self, o):
+        o = self._coerce(o)
+        r = dict(self.t)
+        for k, v in o.t.items():
+            r[k] = r.get(k, Fr(0)) + v
+        return Lin(r)
+
+    __radd__ = __add__
+
+    def __neg__(self):
+        return Lin({k: -v for k, v in self.t.items()})
+
+    def __sub__(self, o):
+        return self + (-self._coerce(o))
+
+    def __rsub__(self, o):
+        return self._coerce(o) - self
+
+    def __mul__(self, s):
+        return Lin({k: v * Fr(s) for k, v in self.t.items()})
+
+    __rmul__ = __mul__
+
+    def clean(self):
+        return {k: v for k, v in self.t.items() if v != 0}
+
+
+class _Sym:
+    def __init__(self, r):
+        self.r = r
+
+    def __getitem__(self, idx):
+        return Lin({(self.r, idx): Fr(1)})
+
+
+def _fracify(expr):
+    return re.sub(r"(\d+)/(\d+)", r"Fr(\1,\2)", expr)
+
+
+def parse_forms(name):
+    """Return {section: {lhs: Lin}} for files of `lhs = linear expression` lines."""
+    out, sec = {}, ""
+    env = {"Fr": Fr, "u0": _Sym(0), "u1": _Sym(1), "u2": _Sym(2), "__builtins__": {}}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("["):
+                sec = line.strip("[]")
+                continue
+            lhs, rhs = (s.strip() for s in line.split("=", 1))
+            out.setdefault(sec, {})[lhs] = eval(_fracify(rhs), env).clean()
+    return out
+
+
+def parse_matrices(name):
+    """Return {lhs: nested lists of Fractions} for `lhs = [[a/b, ...], ...]` lines."""
+    out = {}
+    env = {"Fr": Fr, "__builtins__": {}}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            lhs, rhs = (s.strip() for s in line.split("=", 1))
+            rhs = re.sub(r"(-?\d+)/(\d+)", r"Fr(\1,\2)", rhs)
+            rhs = re.sub(r"(?<![\w(,])(-?\d+)(?![\w/,)]*\))", r"\1", rhs)
+            out[lhs] = _to_fr(eval(rhs, env))
+    return out
+
+
+def _to_fr(x):
+    if isinstance(x, list):
+        return [_to_fr(v) for v in x]
+    return Fr(x)
+
+
+def parse_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows.append((parts[0], int(parts[1]), [float(v) for v in parts[2:]]))
+    return rows

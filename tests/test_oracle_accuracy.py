@@ -1,0 +1,116 @@
+"""Accuracy pins of the oracle against the paper's convergence claims and printed errors.
+
+* Prop. 3.3 (cell-average superconvergence of the linear backbone): on sine
+  advection with OE off and dt ~ dx^{(k+1)/3} (so RK3's error does not mask the
+  spatial one), averages converge with order k+1 and first moments with order k.
+* Prop. 2.2(ii): the OE pass does not reduce the order (sine advection, OE Type II).
+* Tables 1dBur and 1dEuler (smooth Burgers, smooth 1D Euler, OE Type II,
+  C = 0.1, dt = C dx^{k/3}/alpha): errors of the density averages (mean absolute
+  error over cells) within stated factors of the printed values.  The Burgers
+  FAM5/FAM6 rows are reproduced to a few percent, which also pins the global
+  Lax-Friedrichs reading of the numerical flux.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import fam_inputs as fi
+from golden_util import parse_table
+from oracle.scheme import Config, run, step
+
+GOLD = parse_table("smooth_accuracy_tables.txt")
+
+
+def _sine_errors(k, n, dt_rule, oe):
+    cfg = Config(dim=1, nx=n, k=k, system="advection", oe=oe, x0=0.0, x1=2 * math.pi)
+    T = 2 * math.pi
+    dt0 = dt_rule(cfg.dx)
+    nsteps = int(math.ceil(T / dt0 - 1e-9))
+    U, _, _ = run(torch.tensor(fi.sine_advection(n)), cfg, nsteps=nsteps, dt=T / nsteps)
+    ex = fi.sine_advection(n)   # one period later the exact solution is the initial one
+    e0 = np.abs(U[0, 0].numpy() - ex[0, 0]).mean()
+    e1 = np.abs(U[0, 1].numpy() - ex[0, 1]).mean()
+    return e0, e1
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_cell_average_superconvergence(k):
+    ns = (40, 80, 160)
+    errs = [_sine_errors(k, n, lambda dx: 0.2 * dx ** ((k + 1) / 3), "off") for n in ns]
+    o0 = math.log2(errs[1][0] / errs[2][0])
+    o1 = math.log2(errs[1][1] / errs[2][1])
+    assert o0 > k + 1 - 0.25, (k, errs)
+    assert k - 0.3 < o1 < k + 0.6, (k, errs)
+
+
+def test_oe_keeps_the_order_on_sine_advection():
+    """Sine advection at dt = 0.2 dx (5N steps to t = 2 pi): FAM3 with OE Type II."""
+    ns = (50, 100, 200)
+    errs = [_sine_errors(3, n, lambda dx: 0.2 * dx, "type2") for n in ns]
+    o0 = math.log2(errs[1][0] / errs[2][0])
+    o1 = math.log2(errs[1][1] / errs[2][1])
+    # averages: RK3's O(dt^3) error dominates at dt = 0.2 dx; moments: order k.
+    # (The Type II denominator vanishes at the zero crossings of this data, so the
+    # premise of Prop. 2.2(ii) fails locally; only the orders are asserted.)
+    assert o0 > 2.9 and o1 > 2.8, errs
+
+
+def _smooth_run(system, k, n, T, U0):
+    x1 = 2.0
+    cfg = Config(dim=1, nx=n, x0=0.0, x1=x1, k=k, system=system, oe="type2")
+    U = torch.tensor(U0)
+    t = 0.0
+    while t < T:
+        alpha = float(torch.max(cfg.phys.speed(U[:, 0], 0)))
+        dt = min(0.1 * cfg.dx ** (k / 3) / alpha, T - t)
+        U, _ = step(U, cfg, dt)
+        t += dt
+    return U
+
+
+def _gold(table, n, k):
+    for name, nn, vals in GOLD:
+        if name == table and nn == n:
+            return vals[k - 3]
+    raise KeyError((table, n))
+
+
+@pytest.mark.parametrize("k,tol", [(3, 1.6), (4, 1.8), (5, 1.1), (6, 1.1)])
+def test_burgers_table(k, tol):
+    T = 0.5 / math.pi
+    errs = []
+    for n in (30, 60):
+        U = _smooth_run("burgers", k, n, T, fi.burgers_smooth(n))
+        e = np.abs(U[0, 0].numpy() - fi.burgers_exact_moments(n, T)[0, 0]).mean()
+        g = _gold("burgers_avg", n, k)
+        assert g / tol < e < g * tol, (k, n, e, g)
+        errs.append(e)
+
+
+@pytest.mark.parametrize("k,ns", [(3, (20, 30)), (5, (20,))])
+def test_euler_1d_table(k, ns):
+    for n in ns:
+        U = _smooth_run("euler", k, n, 2.0, fi.smooth_euler_1d(n))
+        e = np.abs(U[0, 0].numpy() - fi.smooth_euler_1d_exact_density(n, 2.0)[0, 0]).mean()
+        g = _gold("euler1d_avg", n, k)
+        assert g / 2.5 < e < g * 2.5, (k, n, e, g)
+
+
+@pytest.mark.skipif(os.environ.get("FAM_SLOW") != "1", reason="about a minute of CPU; set FAM_SLOW=1")
+def test_euler_2d_table_fam5():
+    n, k, T = 20, 5, 2.0
+    cfg = Config(dim=2, nx=n, ny=n, x0=0, x1=2, y0=0, y1=2, k=k, system="euler", oe="type2")
+    U = torch.tensor(fi.smooth_euler_2d(n))
+    t = 0.0
+    while t < T:
+        ax = float(torch.max(cfg.phys.speed(U[:, 0], 0)))
+        ay = float(torch.max(cfg.phys.speed(U[:, 0], 1)))
+        dt = min(0.1 / (ax / cfg.dx ** (k / 3) + ay / cfg.dy ** (k / 3)), T - t)
+        U, _ = step(U, cfg, dt)
+        t += dt
+    e = np.abs(U[0, 0].numpy() - fi.smooth_euler_2d_exact_density(n, T)[0, 0]).mean()
+    g = _gold("euler2d_avg", n, k)
+    assert g / 3 < e < g * 3, (e, g)
