@@ -1,0 +1,152 @@
+/*
+ * fam.h - C ABI of the MI355X (gfx950) library for the compact
+ * finite-average-moment (FAM) scheme with single-step oscillation elimination.
+ *
+ * Method (all section / equation / table labels refer to the FAM paper):
+ *  - evolved state: cell average and scaled first moments of every conserved
+ *    component (Sec. 2.1 for 1D, Sec. 2.2 for 2D);
+ *  - each SSP-RK3 stage (eq. 3 / eq. 12) evaluates the semi-discrete operator
+ *    of eq. (1dSemi) / eq. (11): componentwise compact linear reconstruction of
+ *    order k = 3..6 (Sec. 2.4), Lax-Friedrichs (Rusanov) flux at 4 Gauss points
+ *    per face, 4x4 Gauss quadrature of the first-moment volume term;
+ *  - after the last stage one OE pass (Prop. 2.1; eqs. 1dOE_system,
+ *    2dOE_system; Tables sigma1d / sigma2d) keeps the cell averages and damps
+ *    the first moments by exp(-beta dt sigma / dx).
+ *
+ * Memory layout of a state U (all doubles, structure of arrays):
+ *   U[((c * M) + m) * ny * nx + j * nx + i]
+ * with component c (scalar laws: 1; 1D Euler: rho, rho u, E; 2D Euler: rho,
+ * rho u, rho v, E), moment m (M = 2 in 1D: average, x-moment; M = 3 in 2D:
+ * average, x-moment, y-moment), row j < ny (ny = 1 in 1D) and column i < nx.
+ * A batched context stores its instances one after another in one buffer, each
+ * in the layout above (fam_instance_offset gives the start of each).
+ *
+ * Ownership: every pointer to state data is a DEVICE pointer owned by the
+ * caller.  The library owns its scratch (two stage buffers, reduction slots,
+ * the adjoint's checkpoints and tapes), allocated in fam_init / fam_init_batched
+ * / on the first fam_adjoint call and freed by fam_destroy.
+ *
+ * Streams: all work is enqueued on the stream given to fam_init (NULL: the
+ * default stream).  fam_step and fam_stage / fam_oe / fam_dt are asynchronous;
+ * fam_run, fam_check and fam_adjoint synchronise the stream before returning.
+ * Calls on one context must not overlap.
+ *
+ * Errors: functions return a fam_status and never throw.  A non-physical state
+ * (a cell average used for a wave speed with rho <= 0, p <= 0 or not finite)
+ * raises a device flag; fam_run and fam_check report it as FAM_ERR_NONPHYSICAL.
+ */
+#ifndef FAM_H
+#define FAM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FAM_OK = 0,
+  FAM_ERR_ARG = -1,          /* invalid argument or configuration            */
+  FAM_ERR_DEVICE = -2,       /* a HIP call failed                            */
+  FAM_ERR_NOMEM = -3,        /* device allocation failed                     */
+  FAM_ERR_NONPHYSICAL = -4,  /* inadmissible cell average met (device flag)  */
+  FAM_ERR_STATE = -5         /* call not valid for this context              */
+} fam_status;
+
+typedef enum { FAM_ADVECTION = 0, FAM_BURGERS = 1, FAM_EULER = 2 } fam_system;
+typedef enum { FAM_BC_PERIODIC = 0, FAM_BC_TRANSMISSIVE = 1 } fam_bc;
+typedef enum { FAM_OE_OFF = 0, FAM_OE_TYPE1 = 1, FAM_OE_TYPE2 = 2 } fam_oe_type;
+
+typedef struct {
+  int dim;                /* 1 or 2                                               */
+  int nx, ny;             /* cells; ny is ignored (1) when dim == 1               */
+  double x0, x1, y0, y1;  /* domain [x0,x1] x [y0,y1]                             */
+  int k;                  /* order 3..6 (Sec. 2.4)                                */
+  int system;             /* fam_system                                           */
+  double gamma;           /* ratio of specific heats (Euler)                      */
+  double ax, ay;          /* advection velocity                                   */
+  int bc_x, bc_y;         /* fam_bc: periodic, or transmissive (two ghost layers
+                             copying every moment of the nearest interior cell;
+                             Remark after Algorithm 1)                            */
+  int oe;                 /* fam_oe_type                                          */
+  double oe_gamma_k;      /* <= 0: the paper's gamma_k (1D 25/25/12.5/12.5,
+                             2D 25/25/15/15 for k = 3..6; Secs. 2.1, 2.2)         */
+  double cfl;             /* C of the time step dt = C dx/alpha_x (1D) or
+                             C/(alpha_x/dx + alpha_y/dy) (2D) (Sec. 4)            */
+  int k6_jump_from_table; /* k = 6, 2D: 0 = OE jumps of p_6 (the text's u_h^*),
+                             1 = jumps of the full auxiliary Q_6, which is what
+                             the printed matrices A_6, B_6, C_6 encode           */
+} fam_config;
+
+typedef struct fam_ctx fam_ctx;
+
+/* Validate cfg, allocate scratch, bind the HIP stream (hipStream_t or NULL). */
+fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx** out);
+
+/* A context advancing n_inst independent 2D instances together (one launch per
+ * RK stage and one OE launch for all of them).  All instances share dim = 2,
+ * k, system, gamma, oe, cfl and the boundary conditions; sizes and domains may
+ * differ.  Every instance uses its own time step. */
+fam_status fam_init_batched(const fam_config* per_instance, int n_inst, void* hip_stream,
+                            fam_ctx** out);
+
+/* Number of doubles in a state (sum over instances for a batched context). */
+size_t fam_state_len(const fam_ctx* ctx);
+/* Offset (in doubles) of instance i inside a batched state; 0 for i = 0. */
+size_t fam_instance_offset(const fam_ctx* ctx, int i);
+int fam_num_instances(const fam_ctx* ctx);
+
+/* One full step in place on U: CFL time step (unless dt_fixed > 0), three
+ * SSP-RK3 stages, OE.  If dt_used_dev is not NULL the time step used is stored
+ * there (device memory; one double per instance).  Asynchronous. */
+fam_status fam_step(fam_ctx* ctx, double* U, double dt_fixed, double* dt_used_dev);
+
+/* Advance U in place until t_final (the last step clipped to land on it) or
+ * until max_steps steps, whichever comes first (t_final <= 0: max_steps steps).
+ * dt_fixed > 0 replaces the CFL rule.  Steps are enqueued in chunks replayed
+ * from a captured HIP graph; the stream is synchronised between chunks to test
+ * for termination and non-physical states.  For a batched context every
+ * instance runs to t_final (each with its own dt), and steps_done is the
+ * largest per-instance count. */
+fam_status fam_run(fam_ctx* ctx, double* U, double t_final, int max_steps, double dt_fixed,
+                   int* steps_done, double* t_done);
+
+/* Building blocks of one step, for tests and profiling (asynchronous):
+ * fam_dt:    dt_dev[inst] = CFL time step of U (or dt_fixed if > 0); also primes
+ *            the wave-speed reduction used by the next fam_stage(s = 0).
+ * fam_stage: Uout = a_s U0 + b_s (Us + dt R(Us)) with (a_s, b_s) = (0, 1),
+ *            (3/4, 1/4), (1/3, 2/3) for s = 0, 1, 2 (eq. 12).  Uout must not
+ *            alias Us.  Call in order s = 0, 1, 2 after fam_dt.
+ * fam_oe:    Uout = OE(Un) with the time step in dt_dev (Uout must not alias Un). */
+fam_status fam_dt(fam_ctx* ctx, const double* U, double dt_fixed, double* dt_dev);
+fam_status fam_stage(fam_ctx* ctx, int s, const double* U0, const double* Us, double* Uout,
+                     const double* dt_dev);
+fam_status fam_oe(fam_ctx* ctx, const double* Un, double* Uout, const double* dt_dev);
+
+/* Synchronise and report the device flag (FAM_OK or FAM_ERR_NONPHYSICAL);
+ * clears the flag. */
+fam_status fam_check(fam_ctx* ctx);
+
+/* Gradient of a final-time functional J(U_T) with respect to the initial state
+ * U0 after nsteps steps with the fixed time step dt (not differentiated), by
+ * hand-written adjoint kernels of the OE, the three RK stages and R(U), with a
+ * checkpoint every checkpoint_every steps and recomputation of each segment.
+ * dJdUT: device pointer to dJ/dU_T, or NULL for the built-in functional
+ * J = integral over [1/4,3/4]^2 of rho_h(T)^2 = sum over cells with centres in
+ * the window of dx dy (rho0^2 + 12 rho1^2 + 12 rho2^2) (2D only).
+ * dJdU0: device output, same layout as U0.  J_out (host, may be NULL) receives
+ * J for the built-in functional.  Non-smooth points use one-sided choices:
+ * |x|' = sign(x) with sign(0) = 0, maxima pass the derivative to their first
+ * maximal entry, the zero-denominator branch of the OE coefficient has zero
+ * derivative.  Synchronous.  Single-instance 2D contexts only. */
+fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
+                       int checkpoint_every, const double* dJdUT, double* dJdU0, double* J_out);
+
+void fam_destroy(fam_ctx* ctx);
+const char* fam_status_str(fam_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FAM_H */

@@ -1,0 +1,549 @@
+// fam_api.hip - host side of the FAM library: the C ABI of include/fam.h.
+//
+// A context owns two stage buffers W1, W2 (the SSP-RK3 stage states), one
+// StepState per instance (wave-speed maxima per stage, time step, time, step
+// count, termination), a non-physical flag, Type I statistics scratch and, for
+// batched contexts, device tables of instances and of the work list
+// (instance, strip origin, row origin, rows) that the persistent kernels walk.
+//
+// Step sequence (one stream, no host synchronisation):
+//   [alpha reduction of U]  step_begin  stage0: U -> W1  stage1: (W1, U) -> W2
+//   stage2: (W2, U) -> W1 (or -> U when OE is off)  [Type I stats]  OE: W1 -> U
+// The wave speeds of each stage's output are reduced inside the stage kernel;
+// the last stage's are those of the next step's state (OE keeps averages), so
+// consecutive steps need no separate reduction pass.  Two consecutive steps
+// (stage-slot parity 0 and 1) are captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/fam.h"
+#include "fam_kernels.h"
+
+using fam::Inst;
+using fam::StepState;
+
+struct fam_ctx {
+  std::vector<fam_config> cfg;
+  int ninst = 0;
+  int dim = 2, k = 5, sys = 2, nc = 4, nmom = 3, oe = 2, bcx = 0, bcy = 0, k6t = 0;
+  double gamma_k = 15.0;
+  fam::PhysParams phys{1.4, 1.0, 0.0};
+  hipStream_t stream = nullptr;
+  std::vector<size_t> offsets;
+  size_t len = 0, max_cells = 0;
+  double* W1 = nullptr;
+  double* W2 = nullptr;
+  StepState* st = nullptr;
+  int* flag = nullptr;
+  double* stats = nullptr;     // Type I: [inst*8 + ...]
+  double* partial = nullptr;   // Type I partial sums
+  double* dmax = nullptr;
+  int t1_blocks = 256;
+  int H = 32;                  // rows per strip tile (single instance)
+  // batched
+  Inst* d_insts[2][4] = {};    // [parity][stage 0..2, 3 = OE]
+  Inst* d_ainst[2] = {};       // [parity]: alpha_out = stage-0 input slot
+  int4* d_work = nullptr;
+  int nwork = 0;
+  int pblocks = 0;             // persistent grid size
+  std::vector<int> inst_H;
+  // graphs (keyed by U pointer, dt_fixed, t_final)
+  struct GKey {
+    double* U;
+    double dt_fixed, t_final;
+    bool operator<(const GKey& o) const {
+      if (U != o.U) return U < o.U;
+      if (dt_fixed != o.dt_fixed) return dt_fixed < o.dt_fixed;
+      return t_final < o.t_final;
+    }
+  };
+  std::map<GKey, hipGraphExec_t> graphs;
+  bool use_graph = true;
+  // adjoint scratch
+  void* adj = nullptr;
+};
+
+extern "C" const char* fam_status_str(fam_status s) {
+  switch (s) {
+    case FAM_OK: return "ok";
+    case FAM_ERR_ARG: return "invalid argument";
+    case FAM_ERR_DEVICE: return "HIP error";
+    case FAM_ERR_NOMEM: return "out of device memory";
+    case FAM_ERR_NONPHYSICAL: return "non-physical state (rho <= 0 or p <= 0 in a cell average)";
+    case FAM_ERR_STATE: return "call not valid for this context";
+  }
+  return "unknown status";
+}
+
+#define HIP_TRY(expr)                       \
+  do {                                      \
+    if ((expr) != hipSuccess) return FAM_ERR_DEVICE; \
+  } while (0)
+
+static fam_status validate(const fam_config& c) {
+  if (c.dim != 1 && c.dim != 2) return FAM_ERR_ARG;
+  if (c.nx < 3 || (c.dim == 2 && c.ny < 3)) return FAM_ERR_ARG;
+  if (c.k < 3 || c.k > 6) return FAM_ERR_ARG;
+  if (c.system < 0 || c.system > 2) return FAM_ERR_ARG;
+  if (!(c.x1 > c.x0) || (c.dim == 2 && !(c.y1 > c.y0))) return FAM_ERR_ARG;
+  if (c.bc_x < 0 || c.bc_x > 1 || c.bc_y < 0 || c.bc_y > 1) return FAM_ERR_ARG;
+  if (c.oe < 0 || c.oe > 2) return FAM_ERR_ARG;
+  if (!(c.cfl > 0.0)) return FAM_ERR_ARG;
+  if (c.system == FAM_EULER && !(c.gamma > 1.0)) return FAM_ERR_ARG;
+  if ((size_t)c.nx * (size_t)(c.dim == 2 ? c.ny : 1) > ((size_t)1 << 31)) return FAM_ERR_ARG;
+  return FAM_OK;
+}
+
+static double default_gamma_k(int dim, int k) {
+  if (dim == 1) return k <= 4 ? 25.0 : 12.5;
+  return k <= 4 ? 25.0 : 15.0;
+}
+
+static Inst make_inst(const fam_ctx* c, int i) {
+  const fam_config& f = c->cfg[i];
+  Inst in{};
+  in.id = i;
+  in.nx = f.nx;
+  in.ny = c->dim == 2 ? f.ny : 1;
+  in.plane = (size_t)in.nx * in.ny;
+  in.offset = c->offsets[i];
+  in.dx = (f.x1 - f.x0) / f.nx;
+  in.dy = c->dim == 2 ? (f.y1 - f.y0) / f.ny : 1.0;
+  in.bcx = f.bc_x;
+  in.bcy = f.bc_y;
+  return in;
+}
+
+static Inst inst_for(const fam_ctx* c, int i, int parity, int stage) {
+  Inst in = make_inst(c, i);
+  StepState* s = c->st + i;
+  if (stage < 3) {
+    in.alpha_in = &s->alpha[parity][stage][0];
+    in.alpha_out = stage < 2 ? &s->alpha[parity][stage + 1][0] : &s->alpha[1 - parity][0][0];
+  } else {
+    in.alpha_in = &s->alpha[parity][0][0];
+    in.alpha_out = nullptr;
+  }
+  in.dt = &s->dt;
+  in.done = &s->done;
+  return in;
+}
+
+// rows per strip tile: enough tiles to fill 256 CUs several times over
+static int choose_H(int nx, int ny) {
+  const int strips = (nx + 61) / 62;
+  int H = 32;
+  while (H > 8 && (size_t)strips * ((ny + H - 1) / H) < 8 * 256) H /= 2;
+  return std::min(H, std::max(ny, 1));
+}
+
+static fam_status alloc_common(fam_ctx* c) {
+  const size_t bytes = c->len * sizeof(double);
+  if (hipMalloc(&c->W1, bytes) != hipSuccess) return FAM_ERR_NOMEM;
+  if (hipMalloc(&c->W2, bytes) != hipSuccess) return FAM_ERR_NOMEM;
+  if (hipMalloc(&c->st, sizeof(StepState) * c->ninst) != hipSuccess) return FAM_ERR_NOMEM;
+  if (hipMalloc(&c->flag, sizeof(int) * 4) != hipSuccess) return FAM_ERR_NOMEM;
+  if (hipMalloc(&c->stats, sizeof(double) * 8 * c->ninst) != hipSuccess) return FAM_ERR_NOMEM;
+  if (hipMalloc(&c->partial, sizeof(double) * 4 * c->t1_blocks) != hipSuccess) return FAM_ERR_NOMEM;
+  if (hipMalloc(&c->dmax, sizeof(double) * 8) != hipSuccess) return FAM_ERR_NOMEM;
+  std::vector<int> zero(4, 0);
+  HIP_TRY(hipMemcpy(c->flag, zero.data(), sizeof(int) * 4, hipMemcpyHostToDevice));
+  return FAM_OK;
+}
+
+// one-time: the static fields of every instance's StepState (synchronous)
+static fam_status init_steps(fam_ctx* c) {
+  std::vector<StepState> h(c->ninst);
+  for (int i = 0; i < c->ninst; ++i) {
+    StepState& s = h[i];
+    std::memset(&s, 0, sizeof(s));
+    const fam_config& f = c->cfg[i];
+    s.cfl = f.cfl;
+    s.dx = (f.x1 - f.x0) / f.nx;
+    s.dy = c->dim == 2 ? (f.y1 - f.y0) / f.ny : 1.0;
+    s.dim = c->dim;
+  }
+  HIP_TRY(hipMemcpy(c->st, h.data(), sizeof(StepState) * c->ninst, hipMemcpyHostToDevice));
+  return FAM_OK;
+}
+
+// per run: time, step count, termination and wave-speed slots back to zero
+static fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed) {
+  fam::launch_reset_steps(c->st, c->ninst, t_final, dt_fixed, c->stream);
+  return FAM_OK;
+}
+
+static fam_status build_inst_tables(fam_ctx* c) {
+  for (int p = 0; p < 2; ++p) {
+    for (int s = 0; s < 4; ++s) {
+      std::vector<Inst> h(c->ninst);
+      for (int i = 0; i < c->ninst; ++i) h[i] = inst_for(c, i, p, s);
+      if (hipMalloc(&c->d_insts[p][s], sizeof(Inst) * c->ninst) != hipSuccess) return FAM_ERR_NOMEM;
+      HIP_TRY(hipMemcpy(c->d_insts[p][s], h.data(), sizeof(Inst) * c->ninst, hipMemcpyHostToDevice));
+    }
+    std::vector<Inst> h(c->ninst);
+    for (int i = 0; i < c->ninst; ++i) {
+      h[i] = inst_for(c, i, p, 0);
+      h[i].alpha_out = const_cast<double*>(h[i].alpha_in);
+    }
+    if (hipMalloc(&c->d_ainst[p], sizeof(Inst) * c->ninst) != hipSuccess) return FAM_ERR_NOMEM;
+    HIP_TRY(hipMemcpy(c->d_ainst[p], h.data(), sizeof(Inst) * c->ninst, hipMemcpyHostToDevice));
+  }
+  return FAM_OK;
+}
+
+static void destroy_graphs(fam_ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+void fam_adjoint_free(fam_ctx* c);
+
+extern "C" void fam_destroy(fam_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  fam_adjoint_free(c);
+  hipFree(c->W1);
+  hipFree(c->W2);
+  hipFree(c->st);
+  hipFree(c->flag);
+  hipFree(c->stats);
+  hipFree(c->partial);
+  hipFree(c->dmax);
+  for (auto& a : c->d_insts)
+    for (auto* p : a) hipFree(p);
+  for (auto* p : c->d_ainst) hipFree(p);
+  hipFree(c->d_work);
+  delete c;
+}
+
+static void set_common(fam_ctx* c, const fam_config& f) {
+  c->dim = f.dim;
+  c->k = f.k;
+  c->sys = f.system;
+  c->nc = f.system == FAM_EULER ? f.dim + 2 : 1;
+  c->nmom = f.dim == 1 ? 2 : 3;
+  c->oe = f.oe;
+  c->bcx = f.bc_x;
+  c->bcy = f.bc_y;
+  c->k6t = f.k6_jump_from_table;
+  c->gamma_k = f.oe_gamma_k > 0 ? f.oe_gamma_k : default_gamma_k(f.dim, f.k);
+  c->phys = fam::PhysParams{f.gamma, f.ax, f.ay};
+}
+
+extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx** out) {
+  if (!cfg || !out) return FAM_ERR_ARG;
+  *out = nullptr;
+  fam_status v = validate(*cfg);
+  if (v != FAM_OK) return v;
+  fam_ctx* c = new (std::nothrow) fam_ctx();
+  if (!c) return FAM_ERR_NOMEM;
+  fam_config f = *cfg;
+  if (f.dim == 1) { f.ny = 1; f.y0 = 0.0; f.y1 = 1.0; }
+  c->cfg = {f};
+  c->ninst = 1;
+  set_common(c, f);
+  c->stream = (hipStream_t)hip_stream;
+  c->use_graph = c->stream != nullptr;
+  c->offsets = {0};
+  c->max_cells = (size_t)f.nx * (f.dim == 2 ? f.ny : 1);
+  c->len = c->max_cells * c->nc * c->nmom;
+  c->H = f.dim == 2 ? choose_H(f.nx, f.ny) : 1;
+  fam_status a = alloc_common(c);
+  if (a == FAM_OK) a = init_steps(c);
+  if (a == FAM_OK) a = build_inst_tables(c);
+  if (a != FAM_OK) {
+    fam_destroy(c);
+    return a;
+  }
+  *out = c;
+  return FAM_OK;
+}
+
+extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_stream, fam_ctx** out) {
+  if (!per || !out || n < 1) return FAM_ERR_ARG;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    fam_status v = validate(per[i]);
+    if (v != FAM_OK) return v;
+    const fam_config &a = per[0], &b = per[i];
+    if (b.dim != 2 || b.k != a.k || b.system != a.system || b.gamma != a.gamma || b.oe != a.oe ||
+        b.bc_x != a.bc_x || b.bc_y != a.bc_y || b.cfl != a.cfl || b.oe_gamma_k != a.oe_gamma_k ||
+        b.k6_jump_from_table != a.k6_jump_from_table || b.ax != a.ax || b.ay != a.ay)
+      return FAM_ERR_ARG;
+  }
+  if (per[0].oe == FAM_OE_TYPE1) return FAM_ERR_ARG;   // global statistics per instance: single contexts only
+  fam_ctx* c = new (std::nothrow) fam_ctx();
+  if (!c) return FAM_ERR_NOMEM;
+  c->cfg.assign(per, per + n);
+  c->ninst = n;
+  set_common(c, per[0]);
+  c->stream = (hipStream_t)hip_stream;
+  c->use_graph = c->stream != nullptr;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    c->offsets.push_back(off);
+    const size_t cells = (size_t)per[i].nx * per[i].ny;
+    c->max_cells = std::max(c->max_cells, cells);
+    off += cells * c->nc * c->nmom;
+  }
+  c->len = off;
+  fam_status a = alloc_common(c);
+  if (a == FAM_OK) a = init_steps(c);
+  if (a == FAM_OK) a = build_inst_tables(c);
+  if (a != FAM_OK) {
+    fam_destroy(c);
+    return a;
+  }
+  // work list: (instance, i0, j0, H) tiles, largest instances first
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (size_t)per[x].nx * per[x].ny > (size_t)per[y].nx * per[y].ny;
+  });
+  std::vector<int4> work;
+  c->inst_H.assign(n, 16);
+  for (int i : order) {
+    const int H = std::min(16, per[i].ny);
+    c->inst_H[i] = H;
+    for (int j0 = 0; j0 < per[i].ny; j0 += H)
+      for (int i0 = 0; i0 < per[i].nx; i0 += 62) work.push_back(make_int4(i, i0, j0, H));
+  }
+  c->nwork = (int)work.size();
+  c->pblocks = std::min(c->nwork, 256 * 8);
+  if (hipMalloc(&c->d_work, sizeof(int4) * work.size()) != hipSuccess) { fam_destroy(c); return FAM_ERR_NOMEM; }
+  if (hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    fam_destroy(c);
+    return FAM_ERR_DEVICE;
+  }
+  *out = c;
+  return FAM_OK;
+}
+
+extern "C" size_t fam_state_len(const fam_ctx* c) { return c ? c->len : 0; }
+extern "C" size_t fam_instance_offset(const fam_ctx* c, int i) {
+  return (c && i >= 0 && i < c->ninst) ? c->offsets[i] : 0;
+}
+extern "C" int fam_num_instances(const fam_ctx* c) { return c ? c->ninst : 0; }
+
+// ---------------------------------------------------------------------------
+// enqueue helpers
+// ---------------------------------------------------------------------------
+static void enqueue_alpha_full(fam_ctx* c, const double* U, int parity) {
+  fam::launch_zero_alpha(c->st, c->ninst, parity, c->stream);
+  if (c->dim == 1) {
+    Inst in = inst_for(c, 0, parity, 0);
+    in.alpha_out = &c->st[0].alpha[parity][0][0];
+    fam::launch_alpha1d(c->sys, c->phys, U, in, c->flag, c->stream);
+    return;
+  }
+  // the reduction writes into the stage-0 input slot of every instance
+  fam::launch_alpha2d(c->sys, c->phys, U, c->d_ainst[parity], c->ninst, c->max_cells, c->flag, c->stream);
+}
+
+static void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
+                          const double* dt_override) {
+  static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
+  fam::StageArgs A{};
+  A.phys = c->phys;
+  A.Us = Us;
+  A.U0 = U0;
+  A.Uout = Uout;
+  A.ca = CA[s];
+  A.cb = CB[s];
+  A.flag = c->flag;
+  A.done = &c->st[0].done;
+  if (c->ninst == 1) {
+    Inst in = inst_for(c, 0, parity, s);
+    if (dt_override) in.dt = dt_override;
+    if (c->dim == 1)
+      fam::launch_stage1d(c->k, c->sys, A, in, c->stream);
+    else
+      fam::launch_stage2d(c->k, c->sys, A, in, c->H, c->stream);
+  } else {
+    fam::launch_stage2d_batched(c->k, c->sys, A, c->d_insts[parity][s], c->d_work, c->nwork, c->pblocks, c->stream);
+  }
+}
+
+static void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override) {
+  fam::OEArgs A{};
+  A.phys = c->phys;
+  A.Un = Un;
+  A.Uout = Uout;
+  A.gamma_k = c->gamma_k;
+  A.type = c->oe;
+  A.k6_table = c->k6t;
+  A.stats = c->stats;
+  A.flag = c->flag;
+  A.done = &c->st[0].done;
+  if (c->ninst == 1) {
+    Inst in = inst_for(c, 0, parity, 3);
+    if (dt_override) in.dt = dt_override;
+    if (c->oe == FAM_OE_TYPE1)
+      fam::launch_type1_stats(Un, in, c->nc, c->nmom, c->partial, c->t1_blocks, c->dmax, c->stats, c->stream);
+    if (c->dim == 1)
+      fam::launch_oe1d(c->k, c->sys, A, in, c->stream);
+    else
+      fam::launch_oe2d(c->k, c->sys, A, in, c->H, c->stream);
+  } else {
+    fam::launch_oe2d_batched(c->k, c->sys, A, c->d_insts[parity][3], c->d_work, c->nwork, c->pblocks, c->stream);
+  }
+}
+
+static void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_final) {
+  fam::launch_step_begin(c->st, c->ninst, parity, dt_fixed, t_final, c->stream);
+  enqueue_stage(c, 0, parity, U, U, c->W1, nullptr);
+  enqueue_stage(c, 1, parity, U, c->W1, c->W2, nullptr);
+  if (c->oe == FAM_OE_OFF) {
+    enqueue_stage(c, 2, parity, U, c->W2, U, nullptr);
+  } else {
+    enqueue_stage(c, 2, parity, U, c->W2, c->W1, nullptr);
+    enqueue_oe(c, parity, c->W1, U, nullptr);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// public entry points
+// ---------------------------------------------------------------------------
+extern "C" fam_status fam_step(fam_ctx* c, double* U, double dt_fixed, double* dt_used_dev) {
+  if (!c || !U) return FAM_ERR_ARG;
+  fam_status r = reset_steps(c, 0.0, 0.0);
+  if (r != FAM_OK) return r;
+  enqueue_alpha_full(c, U, 0);
+  enqueue_step(c, U, 0, dt_fixed, 0.0);
+  if (dt_used_dev) {
+    for (int i = 0; i < c->ninst; ++i)
+      HIP_TRY(hipMemcpyAsync(dt_used_dev + i, &c->st[i].dt, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+extern "C" fam_status fam_dt(fam_ctx* c, const double* U, double dt_fixed, double* dt_dev) {
+  if (!c || !U || !dt_dev) return FAM_ERR_ARG;
+  fam_status r = reset_steps(c, 0.0, 0.0);
+  if (r != FAM_OK) return r;
+  enqueue_alpha_full(c, U, 0);
+  fam::launch_step_begin(c->st, c->ninst, 0, dt_fixed, 0.0, c->stream);
+  for (int i = 0; i < c->ninst; ++i)
+    HIP_TRY(hipMemcpyAsync(dt_dev + i, &c->st[i].dt, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+extern "C" fam_status fam_stage(fam_ctx* c, int s, const double* U0, const double* Us, double* Uout,
+                                const double* dt_dev) {
+  if (!c || s < 0 || s > 2 || !U0 || !Us || !Uout || !dt_dev || Uout == Us) return FAM_ERR_ARG;
+  if (c->ninst != 1) return FAM_ERR_STATE;
+  enqueue_stage(c, s, 0, U0, Us, Uout, dt_dev);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+extern "C" fam_status fam_oe(fam_ctx* c, const double* Un, double* Uout, const double* dt_dev) {
+  if (!c || !Un || !Uout || !dt_dev || Un == Uout) return FAM_ERR_ARG;
+  if (c->ninst != 1) return FAM_ERR_STATE;
+  if (c->oe == FAM_OE_OFF) {
+    HIP_TRY(hipMemcpyAsync(Uout, Un, c->len * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return FAM_OK;
+  }
+  enqueue_oe(c, 0, Un, Uout, dt_dev);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+extern "C" fam_status fam_check(fam_ctx* c) {
+  if (!c) return FAM_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int h = 0;
+  HIP_TRY(hipMemcpy(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (h) {
+    int z = 0;
+    HIP_TRY(hipMemcpy(c->flag, &z, sizeof(int), hipMemcpyHostToDevice));
+    return FAM_ERR_NONPHYSICAL;
+  }
+  return FAM_OK;
+}
+
+static fam_status get_graph(fam_ctx* c, double* U, double dt_fixed, double t_final, hipGraphExec_t* out) {
+  fam_ctx::GKey key{U, dt_fixed, t_final};
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return FAM_OK;
+  }
+  hipGraph_t g;
+  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  enqueue_step(c, U, 0, dt_fixed, t_final);
+  enqueue_step(c, U, 1, dt_fixed, t_final);
+  HIP_TRY(hipStreamEndCapture(c->stream, &g));
+  hipGraphExec_t ex;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return FAM_ERR_DEVICE;
+  c->graphs[key] = ex;
+  *out = ex;
+  return FAM_OK;
+}
+
+extern "C" fam_status fam_run(fam_ctx* c, double* U, double t_final, int max_steps, double dt_fixed,
+                              int* steps_done, double* t_done) {
+  if (!c || !U || max_steps < 0) return FAM_ERR_ARG;
+  if (!(t_final > 0.0) && max_steps == 0) return FAM_ERR_ARG;
+  const int limit = max_steps > 0 ? max_steps : 0x7fffffff;
+  fam_status r = reset_steps(c, t_final > 0 ? t_final : 0.0, dt_fixed);
+  if (r != FAM_OK) return r;
+  enqueue_alpha_full(c, U, 0);
+  const double tf = t_final > 0 ? t_final : 0.0;
+  int launched = 0;
+  std::vector<StepState> h(c->ninst);
+  int done_steps = 0;
+  double tmin = 0.0;
+  while (launched < limit) {
+    int chunk = std::min(limit - launched, tf > 0 ? 64 : limit);
+    const int pairs = chunk / 2;
+    if (c->use_graph && pairs > 0) {
+      hipGraphExec_t ex;
+      r = get_graph(c, U, dt_fixed, tf, &ex);
+      if (r != FAM_OK) return r;
+      for (int p = 0; p < pairs; ++p) HIP_TRY(hipGraphLaunch(ex, c->stream));
+    } else {
+      for (int p = 0; p < pairs; ++p) {
+        enqueue_step(c, U, 0, dt_fixed, tf);
+        enqueue_step(c, U, 1, dt_fixed, tf);
+      }
+    }
+    if (chunk % 2) enqueue_step(c, U, 0, dt_fixed, tf);
+    launched += chunk;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h.data(), c->st, sizeof(StepState) * c->ninst, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    bool all_done = true;
+    done_steps = 0;
+    tmin = 1e300;
+    for (auto& s : h) {
+      all_done &= (s.done != 0) || (tf > 0 && s.t >= tf);
+      done_steps = std::max(done_steps, s.steps);
+      tmin = std::min(tmin, s.t);
+    }
+    int fl = 0;
+    HIP_TRY(hipMemcpy(&fl, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (fl) {
+      if (steps_done) *steps_done = done_steps;
+      if (t_done) *t_done = tmin;
+      int z = 0;
+      HIP_TRY(hipMemcpy(c->flag, &z, sizeof(int), hipMemcpyHostToDevice));
+      return FAM_ERR_NONPHYSICAL;
+    }
+    if (tf > 0 && all_done) break;
+    if (chunk % 2) break;   // parity would break on another chunk; odd chunks only end a run
+  }
+  if (steps_done) *steps_done = done_steps;
+  if (t_done) *t_done = tmin;
+  return FAM_OK;
+}

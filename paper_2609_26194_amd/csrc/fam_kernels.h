@@ -1,0 +1,89 @@
+// fam_kernels.h - argument blocks and launchers shared by the host library and
+// the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include <algorithm>
+
+namespace fam {
+
+struct PhysParams {
+  double gamma, ax, ay;
+};
+
+// one mesh instance (a batched context holds many)
+struct Inst {
+  int id;
+  int nx, ny;
+  size_t plane;            // nx * ny
+  size_t offset;           // start of the instance in a batched state (doubles)
+  double dx, dy;
+  int bcx, bcy;            // 0 periodic, 1 transmissive
+  const double* alpha_in;  // [2] wave speeds of the stage input state
+  double* alpha_out;       // [2] max-accumulators for the stage output state
+  const double* dt;        // time step of the current step
+  const int* done;         // instance finished (fam_run), may be null
+};
+
+struct StageArgs {
+  PhysParams phys;
+  const double* Us;
+  const double* U0;
+  double* Uout;
+  double ca, cb;           // Uout = ca U0 + cb (Us + dt R(Us))
+  int* flag;
+  const int* done;
+};
+
+struct OEArgs {
+  PhysParams phys;
+  const double* Un;
+  double* Uout;
+  double gamma_k;
+  int type;                // 1 or 2
+  int k6_table;
+  const double* stats;     // Type I: [inst*8 + c] D_Omega, [inst*8 + 4 + c] eps_Omega
+  int* flag;
+  const int* done;
+};
+
+// per-instance step bookkeeping (device)
+struct StepState {
+  double alpha[2][3][2];   // [parity][stage input 0..2][x/y]
+  double dt;               // time step of the current step
+  double t;                // time reached
+  double t_final;          // <= 0: none
+  double dt_fixed;         // > 0: use instead of the CFL rule
+  double cfl;
+  double dx, dy;
+  int dim;
+  int done;
+  int steps;
+  int pad_;
+};
+
+void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, hipStream_t s);
+void launch_oe2d(int k, int sys, const OEArgs& A, const Inst& in, int H, hipStream_t s);
+void launch_stage2d_batched(int k, int sys, const StageArgs& A, const Inst* insts, const int4* work, int nwork,
+                            int nblocks, hipStream_t s);
+void launch_oe2d_batched(int k, int sys, const OEArgs& A, const Inst* insts, const int4* work, int nwork,
+                         int nblocks, hipStream_t s);
+void launch_alpha2d(int sys, const PhysParams& pp, const double* U, const Inst* insts, int ninst,
+                    size_t max_cells, int* flag, hipStream_t s);
+// Type I reference quantities of one instance (nmom = moments per component)
+void launch_type1_stats(const double* U, const Inst& in, int nc, int nmom, double* partial, int nblocks,
+                        double* dmax, double* stats, hipStream_t s);
+
+// 1D
+void launch_stage1d(int k, int sys, const StageArgs& A, const Inst& in, hipStream_t s);
+void launch_oe1d(int k, int sys, const OEArgs& A, const Inst& in, hipStream_t s);
+void launch_alpha1d(int sys, const PhysParams& pp, const double* U, const Inst& in, int* flag, hipStream_t s);
+
+// step bookkeeping: dt, clipping, termination, zeroing of the accumulators
+void launch_step_begin(StepState* st, int ninst, int parity, double dt_fixed, double t_final, hipStream_t s);
+void launch_zero_alpha(StepState* st, int ninst, int parity, hipStream_t s);
+void launch_reset_steps(StepState* st, int ninst, double t_final, double dt_fixed, hipStream_t s);
+
+}  // namespace fam

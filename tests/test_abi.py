@@ -1,0 +1,67 @@
+"""The C-ABI library loads on a machine without a GPU and exports every function
+that include/fam.h declares; status strings and error paths that need no device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2609_26194_amd import fam
+    if not os.path.exists(fam.LIB_PATH):
+        from paper_2609_26194_amd.build import build
+        build()
+    return fam.load_library()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fam.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fam_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("fam_init", "fam_init_batched", "fam_step", "fam_run", "fam_adjoint", "fam_stage", "fam_oe",
+              "fam_dt", "fam_check", "fam_destroy", "fam_state_len", "fam_status_str"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    lib = _lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert len(lib.fam_status_str(code)) > 0
+
+
+def test_invalid_configurations_are_rejected_without_a_device():
+    from paper_2609_26194_amd.fam import FAM_ERR_ARG, FamConfig
+    lib = _lib()
+    h = ctypes.c_void_p()
+    for bad in (dict(dim=3, nx=8, ny=8), dict(dim=2, nx=8, ny=8, k=7), dict(dim=2, nx=2, ny=8),
+                dict(dim=2, nx=8, ny=8, cfl=0.0), dict(dim=2, nx=8, ny=8, gamma=1.0),
+                dict(dim=2, nx=8, ny=8, x0=1.0, x1=0.0)):
+        cfg = FamConfig(**bad)
+        assert lib.fam_init(ctypes.byref(cfg.to_c()), None, ctypes.byref(h)) == FAM_ERR_ARG
+    assert lib.fam_init(None, None, ctypes.byref(h)) == FAM_ERR_ARG
+    assert lib.fam_step(None, None, 0.0, None) == FAM_ERR_ARG
+    assert lib.fam_run(None, None, 1.0, 0, 0.0, None, None) == FAM_ERR_ARG
+
+
+def test_binding_rejects_wrong_sized_states():
+    """The wrapper checks sizes before any launch (no GPU needed for the check itself)."""
+    import torch
+    from paper_2609_26194_amd.fam import Fam
+    fake = Fam.__new__(Fam)
+    fake.len = 10
+    fake.cfgs = [None]
+    with pytest.raises(ValueError):
+        fake._state(torch.zeros(11, dtype=torch.float64))
