@@ -138,7 +138,7 @@ static Inst inst_for(const fam_ctx* c, int i, int parity, int stage) {
 
 // rows per strip tile: enough tiles to fill 256 CUs several times over
 static int choose_H(int nx, int ny) {
-  const int strips = (nx + 61) / 62;
+  const int strips = (nx + fam::STRIP - 1) / fam::STRIP;
   int H = 32;
   while (H > 8 && (size_t)strips * ((ny + H - 1) / H) < 8 * 256) H /= 2;
   return std::min(H, std::max(ny, 1));
@@ -315,7 +315,7 @@ extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_s
     const int H = std::min(16, per[i].ny);
     c->inst_H[i] = H;
     for (int j0 = 0; j0 < per[i].ny; j0 += H)
-      for (int i0 = 0; i0 < per[i].nx; i0 += 62) work.push_back(make_int4(i, i0, j0, H));
+      for (int i0 = 0; i0 < per[i].nx; i0 += fam::STRIP) work.push_back(make_int4(i, i0, j0, H));
   }
   c->nwork = (int)work.size();
   c->pblocks = std::min(c->nwork, 256 * 8);

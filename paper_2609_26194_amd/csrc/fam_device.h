@@ -55,8 +55,8 @@ __host__ __device__ constexpr int maxdeg(int k) { return k - 1; }
 // 11 (k = 3, 4: Q_4) or 23 (k = 5, 6: Q_6); callers keep the ones they need.
 // ---------------------------------------------------------------------------
 template <int K>
-__device__ __forceinline__ void coeffs2d(const double* u0, const double* u1, const double* u2,
-                                         double* c, bool full) {
+__host__ __device__ constexpr inline void coeffs2d(const double* u0, const double* u1, const double* u2,
+                                                   double* c, bool full) {
   // indices 0..8 = patch cells I_1..I_9
   const double a1 = u0[0], a2 = u0[1], a3 = u0[2], a4 = u0[3], a5 = u0[4], a6 = u0[5],
                a7 = u0[6], a8 = u0[7], a9 = u0[8];
@@ -143,6 +143,16 @@ __device__ __forceinline__ void coeffs1d(double u0m, double u00, double u0p, dou
   }
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (relative error within a few units in the last place; not IEEE division)
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // ---------------------------------------------------------------------------
 // Physics
 // ---------------------------------------------------------------------------
@@ -151,6 +161,10 @@ struct Advection {
   double ax, ay;
   __device__ __forceinline__ void flux(int d, const double* u, double* f) const {
     f[0] = (d == 0 ? ax : ay) * u[0];
+  }
+  __device__ __forceinline__ void flux2(const double* u, double* f1, double* f2) const {
+    f1[0] = ax * u[0];
+    f2[0] = ay * u[0];
   }
   __device__ __forceinline__ double speed(int d, const double* u, bool& bad) const {
     bad |= !(u[0] == u[0]);
@@ -163,6 +177,10 @@ struct Burgers {
   double ax, ay;
   __device__ __forceinline__ void flux(int, const double* u, double* f) const {
     f[0] = 0.5 * u[0] * u[0];
+  }
+  __device__ __forceinline__ void flux2(const double* u, double* f1, double* f2) const {
+    f1[0] = 0.5 * u[0] * u[0];
+    f2[0] = f1[0];
   }
   __device__ __forceinline__ double speed(int, const double* u, bool& bad) const {
     bad |= !(u[0] == u[0]);
@@ -181,7 +199,7 @@ struct Euler {
     return (g - 1.0) * (u[NC - 1] - 0.5 * ke * inv_rho);
   }
   __device__ __forceinline__ void flux(int d, const double* u, double* f) const {
-    const double inv = 1.0 / u[0];
+    const double inv = rcp(u[0]);
     const double p = pressure(u, inv);
     const double vel = u[1 + d] * inv;
     f[0] = u[1 + d];
@@ -189,6 +207,23 @@ struct Euler {
     if constexpr (DIM == 2) f[2] = u[2] * vel;
     f[1 + d] += p;
     f[NC - 1] = (u[NC - 1] + p) * vel;
+  }
+  // both directional fluxes at one point (shared 1/rho and pressure)
+  __device__ __forceinline__ void flux2(const double* u, double* f1, double* f2) const {
+    const double inv = rcp(u[0]);
+    const double p = pressure(u, inv);
+    const double vx = u[1] * inv;
+    const double vy = u[DIM == 2 ? 2 : 1] * inv;
+    f1[0] = u[1];
+    f1[1] = u[1] * vx + p;
+    if constexpr (DIM == 2) {
+      f1[2] = u[2] * vx;
+      f2[0] = u[2];
+      f2[1] = u[1] * vy;
+      f2[2] = u[2] * vy + p;
+      f2[3] = (u[3] + p) * vy;
+    }
+    f1[NC - 1] = (u[NC - 1] + p) * vx;
   }
   // spectral radius |u_d| + c at a cell average; flags rho <= 0, p <= 0, NaN
   __device__ __forceinline__ double speed(int d, const double* u, bool& bad) const {

@@ -9,6 +9,8 @@
 
 namespace fam {
 
+constexpr int STRIP = 60;   // output columns per 2D strip (one wavefront)
+
 struct PhysParams {
   double gamma, ax, ay;
 };

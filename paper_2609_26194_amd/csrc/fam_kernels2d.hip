@@ -1,11 +1,11 @@
 // fam_kernels2d.hip - HIP kernels of the 2D FAM step for gfx950.
 //
 // Work decomposition ("marching strips").  One 64-lane wavefront owns a strip of
-// columns: lane l holds column i = i0 - 1 + l.  Lanes 1..62 produce output;
-// lanes 0 and 63 are ring columns whose traces feed the strip's two boundary
-// faces.  The wave marches upwards over the rows j0-1 .. j0+H (the first and last
-// are ring rows), keeping a rolling window of four state rows (12 planes x 66
-// columns) in LDS.  Every face flux is evaluated exactly once per strip:
+// columns: lane l holds column i = i0 - 2 + l.  Lanes 2..61 produce output (60
+// columns); lanes 1 and 62 are ring columns whose traces feed the strip's two
+// boundary faces; lanes 0 and 63 only load.  The wave marches upwards over the
+// rows j0-1 .. j0+H (the first and last are ring rows), keeping a rolling window
+// of three state rows (12 planes x 64 columns) in LDS.  Every face flux is evaluated exactly once per strip:
 //   x-faces: a lane's right trace is passed to the right neighbour lane by a
 //            cross-lane shuffle, and the resulting face flux is passed back;
 //   y-faces: the top trace of row r is kept in registers for row r+1.
@@ -27,13 +27,32 @@
 // of the reconstruction, J^x, J^y, the Type I / Type II denominator over the 3x3
 // patch; sigma = max over components; delta = exp(-beta^x dt sigma^x/dx -
 // beta^y dt sigma^y/dy); first moments scaled by delta, averages copied.
+#include <utility>
+
 #include "fam_device.h"
 #include "fam_kernels.h"
 
 namespace fam {
 
+#ifndef FAM_STAGE_WAVES
+#define FAM_STAGE_WAVES 1
+#endif
+#ifndef FAM_OE_WAVES
+#define FAM_OE_WAVES 1
+#endif
+// occupancy targets (waves per SIMD) handed to the register allocator
+#define FAM_STAGE_ATTR __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FAM_STAGE_WAVES)))
+#define FAM_OE_ATTR __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FAM_OE_WAVES)))
+
+// keeps the scheduler from hoisting the next component's LDS reads above this
+// point (bounds the number of live stencil values)
+#ifndef FAM_NO_FENCE
+#define FAM_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define FAM_SCHED_FENCE() ((void)0)
+#endif
+
 constexpr int LANES = 64;
-constexpr int SCOLS = LANES + 2;   // LDS columns: i0-2 .. i0+63
 constexpr int NPL = 12;            // planes held in LDS for up to 4 components x 3 moments
 
 // Gauss node q = 0..3 at -GS1, -GS0, +GS0, +GS1
@@ -87,58 +106,50 @@ __device__ __forceinline__ double eval_pt(const double (&E)[MD + 1][4], const do
 }
 
 // ---------------------------------------------------------------------------
-// LDS row window
+// LDS row window: lane l holds LDS column l = grid column i0 - 2 + l.  Lanes 0
+// and 63 only load; lanes 1 and 62 are ring columns; lanes 2..61 write output.
 // ---------------------------------------------------------------------------
 struct Window {
-  double v[4][NPL][SCOLS];
+  double v[3][NPL][LANES];
 };
 
-__device__ __forceinline__ int slot_of(int r) { return r & 3; }
+// three row slots used as a ring: row r+2 is fetched into the slot of row r-1
+// once every read of row r-1 in the current iteration is done
+__device__ __forceinline__ int slot_of(int r) { return ((r % 3) + 3) % 3; }
 
-// load row r (BC-mapped) of planes [0, npl) for columns i0-2 .. i0+63 into regs
 template <int NPLU>
-__device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0,
-                                          int r, int lane, double (&reg)[2][NPLU]) {
+__device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0, int r,
+                                          int lane, double (&reg)[NPLU]) {
   const int gj = ghost(r, in.ny, in.bcy);
+  const int gi = ghost(i0 - 2 + lane, in.nx, in.bcx);
+  const size_t base = (size_t)gj * in.nx + gi;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = lane + h * LANES;
-    if (col < SCOLS) {
-      const int gi = ghost(i0 - 2 + col, in.nx, in.bcx);
-      const size_t base = (size_t)gj * in.nx + gi;
-#pragma unroll
-      for (int p = 0; p < NPLU; ++p) reg[h][p] = U[p * in.plane + base];
-    }
-  }
+  for (int p = 0; p < NPLU; ++p) reg[p] = U[p * in.plane + base];
 }
 
 template <int NPLU>
-__device__ __forceinline__ void store_row(Window& W, int slot, int lane, const double (&reg)[2][NPLU]) {
+__device__ __forceinline__ void store_row(Window& W, int slot, int lane, const double (&reg)[NPLU]) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = lane + h * LANES;
-    if (col < SCOLS) {
-#pragma unroll
-      for (int p = 0; p < NPLU; ++p) W.v[slot][p][col] = reg[h][p];
-    }
-  }
+  for (int p = 0; p < NPLU; ++p) W.v[slot][p][lane] = reg[p];
 }
 
-// stencil of component c for the cell in LDS column col, row slots sl (r-1), sm, sh
+// stencil of component c around LDS column col (clamped for the load-only lanes)
 template <int K>
 __device__ __forceinline__ void gather(const Window& W, int c, int col, int sl, int sm, int sh,
                                        double (&u0)[9], double (&u1)[9], double (&u2)[9]) {
   const int sr[3] = {sl, sm, sh};
+  const int cm = col > 0 ? col - 1 : 0, cp = col < LANES - 1 ? col + 1 : LANES - 1;
+  const int cc[3] = {cm, col, cp};
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int l = b * 3 + a;
-      u0[l] = W.v[sr[b]][c * 3 + 0][col - 1 + a];
+      u0[l] = W.v[sr[b]][c * 3 + 0][cc[a]];
       const bool x_used = (K >= 5) ? (l != 1 && l != 7) : (l == 4);
       const bool y_used = (K >= 5) ? (l != 3 && l != 5) : (l == 4);
-      u1[l] = x_used ? W.v[sr[b]][c * 3 + 1][col - 1 + a] : 0.0;
-      u2[l] = y_used ? W.v[sr[b]][c * 3 + 2][col - 1 + a] : 0.0;
+      u1[l] = x_used ? W.v[sr[b]][c * 3 + 1][cc[a]] : 0.0;
+      u2[l] = y_used ? W.v[sr[b]][c * 3 + 2][cc[a]] : 0.0;
     }
 }
 
@@ -153,19 +164,20 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   constexpr int MD = maxdeg(K);
   constexpr int NPLU = NC * 3;
   const int lane = threadIdx.x;
-  const int col = lane + 1;
-  const int i = i0 - 1 + lane;
+  const int col = lane;
+  const int i = i0 - 2 + lane;
   const int rend = min(j0 + H, in.ny);          // exclusive end of output rows
-  const bool out_lane = lane >= 1 && lane <= 62 && i < in.nx;
-  const double dx = in.dx, dy = in.dy;
+  const bool out_lane = lane >= 2 && lane <= LANES - 3 && i < in.nx;
+  const double idx_ = 1.0 / in.dx, idy = 1.0 / in.dy;
+  const double i2dx = 0.5 * idx_, i2dy = 0.5 * idy;
   const double ax = in.alpha_in[0], ay = in.alpha_in[1];
   const double dt = *in.dt;
+  const bool use_u0 = A.ca != 0.0;
   const double* __restrict__ Us = A.Us + in.offset;
   const double* __restrict__ U0 = A.U0 + in.offset;
   double* __restrict__ Uo = A.Uout + in.offset;
 
-  double reg[2][NPLU];
-  // prologue: rows j0-2, j0-1, j0
+  double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
     fetch_row<NPLU>(Us, in, i0, r, lane, reg);
@@ -176,14 +188,24 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   double prevTop[NC][4];     // top trace of the row below (face j-1/2 of the current row)
   double part[NC][3];        // residual of the row below without its top face
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < NC; ++c) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) prevTop[c][q] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) part[c][m] = 0.0;
+  }
 
 #pragma unroll 1
   for (int r = j0 - 1; r <= rend; ++r) {
     const bool pre = (r + 2 <= rend + 1);
     if (pre) fetch_row<NPLU>(Us, in, i0, r + 2, lane, reg);
+    const bool fin = (r - 1 >= j0) && out_lane;   // this iteration finishes row r-1
+    double u0row[NPLU];
+    if (fin && use_u0) {
+      const size_t idx = (size_t)(r - 1) * in.nx + i;
+#pragma unroll
+      for (int p = 0; p < NPLU; ++p) u0row[p] = U0[p * in.plane + idx];
+    }
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1), ring_hi = (r == rend);
 
@@ -197,102 +219,102 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       coeffs2d<K>(u0, u1, u2, tmp, false);
 #pragma unroll
       for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
+      FAM_SCHED_FENCE();
     }
 
-    // traces on the four faces
-    double bt[NC][4], tt[NC][4], lt[NC][4], rt[NC][4];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double E[MD + 1][4], O[MD + 1][3];
-      contract_y<NCF, MD>(cf[c], E, O);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        rt[c][q] = eval_pt<MD>(E, O, 2, 1.0, qnode(q), qsign(q));
-        lt[c][q] = eval_pt<MD>(E, O, 2, -1.0, qnode(q), qsign(q));
-        tt[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
-        bt[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, -1.0);
-      }
-    }
-
-    // y-face below the current row: (i, r-1/2)
+    // bottom trace -> y-face flux below the current row: (i, r-1/2)
     double Gb[NC], Gt[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) Gb[c] = Gt[c] = 0.0;
-    if (!ring_lo) {
+    {
+      double bt[NC][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double ul[NC], ur[NC], fl[NC], fr[NC];
+      for (int c = 0; c < NC; ++c) {
+        double E[MD + 1][4], O[MD + 1][3];
+        contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) { ul[c] = prevTop[c][q]; ur[c] = bt[c][q]; }
-        phys.flux(1, ul, fl);
-        phys.flux(1, ur, fr);
+        for (int q = 0; q < 4; ++q) bt[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, -1.0);
+      }
+      if (!ring_lo) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double fh = 0.5 * (fl[c] + fr[c]) - 0.5 * ay * (ur[c] - ul[c]);
-          Gb[c] = fma(qw(q), fh, Gb[c]);
-          Gt[c] = fma(qw(q) * qx(q), fh, Gt[c]);
+        for (int q = 0; q < 4; ++q) {
+          double ul[NC], ur[NC], fl[NC], fr[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) { ul[c] = prevTop[c][q]; ur[c] = bt[c][q]; }
+          phys.flux(1, ul, fl);
+          phys.flux(1, ur, fr);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double fh = 0.5 * (fl[c] + fr[c]) - 0.5 * ay * (ur[c] - ul[c]);
+            Gb[c] = fma(qw(q), fh, Gb[c]);
+            Gt[c] = fma(qw(q) * qx(q), fh, Gt[c]);
+          }
         }
       }
     }
 
     // finish the row below: its top face is this row's bottom face
-    if (r - 1 >= j0 && out_lane) {
-      const int jj = r - 1;
-      const size_t idx = (size_t)jj * in.nx + i;
-      double nu[NC][3];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const double R0 = part[c][0] - Gb[c] / dy;
-        const double R1 = part[c][1] - Gt[c] / dy;
-        const double R2 = part[c][2] - Gb[c] / (2.0 * dy);
-        const double Rm[3] = {R0, R1, R2};
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const double us = W.v[sl][c * 3 + m][col];
-          const double L = us + dt * Rm[m];
-          double v;
-          if (A.ca == 0.0)
-            v = L;
-          else
-            v = A.ca * U0[(c * 3 + m) * in.plane + idx] + A.cb * L;
-          nu[c][m] = v;
-          Uo[(c * 3 + m) * in.plane + idx] = v;
-        }
-      }
+    if (fin) {
+      const size_t idx = (size_t)(r - 1) * in.nx + i;
       double avg[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) avg[c] = nu[c][0];
+      for (int c = 0; c < NC; ++c) {
+        const double Rm[3] = {part[c][0] - Gb[c] * idy, part[c][1] - Gt[c] * idy, part[c][2] - Gb[c] * i2dy};
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double L = W.v[sl][c * 3 + m][col] + dt * Rm[m];
+          const double v = use_u0 ? A.ca * u0row[c * 3 + m] + A.cb * L : L;
+          Uo[(c * 3 + m) * in.plane + idx] = v;
+          if (m == 0) avg[c] = v;
+        }
+      }
       amax_x = fmax(amax_x, phys.speed(0, avg, bad));
       amax_y = fmax(amax_y, phys.speed(1, avg, bad));
     }
     if (ring_hi) break;
 
-    // carry this row's top trace
+    // top trace of this row (bottom state of the next y-face)
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+      double E[MD + 1][4], O[MD + 1][3];
+      contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) prevTop[c][q] = tt[c][q];
+      for (int q = 0; q < 4; ++q) prevTop[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
+    }
 
     if (!ring_lo) {
       // x-face left of this lane: (i-1/2, r); left state = right trace of lane-1
       double Fb[NC], Ft[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) Fb[c] = Ft[c] = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double ul[NC], ur[NC], fl[NC], fr[NC];
+      {
+        double rt[NC][4], lt[NC][4];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          ul[c] = __shfl_up(rt[c][q], 1, LANES);
-          ur[c] = lt[c][q];
+          double E[MD + 1][4], O[MD + 1][3];
+          contract_y<NCF, MD>(cf[c], E, O);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            rt[c][q] = eval_pt<MD>(E, O, 2, 1.0, qnode(q), qsign(q));
+            lt[c][q] = eval_pt<MD>(E, O, 2, -1.0, qnode(q), qsign(q));
+          }
         }
-        phys.flux(0, ul, fl);
-        phys.flux(0, ur, fr);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double fh = 0.5 * (fl[c] + fr[c]) - 0.5 * ax * (ur[c] - ul[c]);
-          Fb[c] = fma(qw(q), fh, Fb[c]);
-          Ft[c] = fma(qw(q) * qx(q), fh, Ft[c]);
+        for (int q = 0; q < 4; ++q) {
+          double ul[NC], ur[NC], fl[NC], fr[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            ul[c] = __shfl_up(rt[c][q], 1, LANES);
+            ur[c] = lt[c][q];
+          }
+          phys.flux(0, ul, fl);
+          phys.flux(0, ur, fr);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double fh = 0.5 * (fl[c] + fr[c]) - 0.5 * ax * (ur[c] - ul[c]);
+            Fb[c] = fma(qw(q), fh, Fb[c]);
+            Ft[c] = fma(qw(q) * qx(q), fh, Ft[c]);
+          }
         }
       }
       double FbR[NC], FtR[NC];
@@ -318,8 +340,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
           double f1[NC], f2[NC];
-          phys.flux(0, vals[qq], f1);
-          phys.flux(1, vals[qq], f2);
+          phys.flux2(vals[qq], f1, f2);
           const double w = qw(qq) * qw(qy);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
@@ -330,13 +351,13 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        part[c][0] = -(FbR[c] - Fb[c]) / dx + Gb[c] / dy;
-        part[c][1] = V1[c] / dx - (FbR[c] + Fb[c]) / (2.0 * dx) + Gt[c] / dy;
-        part[c][2] = V2[c] / dy + Gb[c] * (-1.0 / (2.0 * dy)) - (FtR[c] - Ft[c]) / dx;
+        part[c][0] = -(FbR[c] - Fb[c]) * idx_ + Gb[c] * idy;
+        part[c][1] = V1[c] * idx_ - (FbR[c] + Fb[c]) * i2dx + Gt[c] * idy;
+        part[c][2] = V2[c] * idy - Gb[c] * i2dy - (FtR[c] - Ft[c]) * idx_;
       }
     }
 
-    // rotate the window: row r+2 replaces row r-2
+    // rotate the window: row r+2 replaces row r-1
     __syncthreads();
     if (pre) store_row<NPLU>(W, slot_of(r + 2), lane, reg);
     __syncthreads();
@@ -345,26 +366,87 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 }
 
 // ---------------------------------------------------------------------------
-// OE tile
+// OE tile.  The four face-centre values of a cell's reconstruction, p(+-1/2, 0)
+// and p(0, +-1/2), are fixed linear functionals of its 3x3 stencil moments; their
+// weights are evaluated at compile time from the same coefficient formulas.
 // ---------------------------------------------------------------------------
-template <int K, class P>
+struct CentreWeights {
+  double w[4][27];   // [r, l, t, b][u0 1..9, u1 1..9, u2 1..9]
+};
+
+template <int K, bool FULL>
+__host__ __device__ constexpr CentreWeights make_centre_weights() {
+  CentreWeights cw{};
+  const double px[4] = {0.5, -0.5, 0.0, 0.0}, py[4] = {0.0, 0.0, 0.5, -0.5};
+  const int ncf = FULL ? 23 : ncoef2d(K);
+  for (int in = 0; in < 27; ++in) {
+    double u[27] = {};
+    u[in] = 1.0;
+    double c[23] = {};
+    coeffs2d<K>(u, u + 9, u + 18, c, FULL);
+    for (int f = 0; f < 4; ++f) {
+      double v = 0.0;
+      for (int l = 0; l < ncf; ++l) v += c[l] * leg(AX[l], px[f]) * leg(AY[l], py[f]);
+      cw.w[f][in] = v;
+    }
+  }
+  return cw;
+}
+
+template <int K, bool FULL>
+struct CentreTable {
+  static constexpr CentreWeights t = make_centre_weights<K, FULL>();
+};
+
+// v += w * u[I] with w a compile-time constant (skipped when zero)
+template <int K, bool FULL, int F, int I>
+__device__ __forceinline__ void centre_acc(double& v, const double (&u)[27]) {
+  constexpr double w = CentreTable<K, FULL>::t.w[F][I];
+  if constexpr (w != 0.0) v = fma(w, u[I], v);
+}
+
+template <int K, bool FULL, int F, int... I>
+__device__ __forceinline__ double centre_dot(const double (&u)[27], std::integer_sequence<int, I...>) {
+  double v = 0.0;
+  (centre_acc<K, FULL, F, I>(v, u), ...);
+  return v;
+}
+
+template <int K, bool FULL>
+__device__ __forceinline__ void centre_values(const Window& W, int c, int col, int sl, int sm, int sh,
+                                              double (&out)[4]) {
+  double u0[9], u1[9], u2[9];
+  gather<K>(W, c, col, sl, sm, sh, u0, u1, u2);
+  double u[27];
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    u[l] = u0[l];
+    u[9 + l] = u1[l];
+    u[18 + l] = u2[l];
+  }
+  using Seq = std::make_integer_sequence<int, 27>;
+  out[0] = centre_dot<K, FULL, 0>(u, Seq{});
+  out[1] = centre_dot<K, FULL, 1>(u, Seq{});
+  out[2] = centre_dot<K, FULL, 2>(u, Seq{});
+  out[3] = centre_dot<K, FULL, 3>(u, Seq{});
+}
+
+template <int K, class P, bool FULL>
 __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, int j0, int H,
                         Window& W, bool& bad) {
   constexpr int NC = P::NC;
-  constexpr int NCF = (K == 6) ? 23 : ncoef2d(K);
-  constexpr int MD = (K == 6) ? 5 : maxdeg(K);
   constexpr int NPLU = NC * 3;
   const int lane = threadIdx.x;
-  const int col = lane + 1;
-  const int i = i0 - 1 + lane;
+  const int col = lane;
+  const int i = i0 - 2 + lane;
   const int rend = min(j0 + H, in.ny);
-  const bool out_lane = lane >= 1 && lane <= 62 && i < in.nx;
+  const bool out_lane = lane >= 2 && lane <= LANES - 3 && i < in.nx;
   const double dt = *in.dt;
-  const bool full = (K == 6) && A.k6_table;
+  const double cx = dt / in.dx, cy = dt / in.dy;
   const double* __restrict__ Un = A.Un + in.offset;
   double* __restrict__ Uo = A.Uout + in.offset;
 
-  double reg[2][NPLU];
+  double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
     fetch_row<NPLU>(Un, in, i0, r, lane, reg);
@@ -375,7 +457,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   double prevTopC[NC];     // face-centre value at the top of the row below
   double prevJb[NC];       // |jump| at the bottom face of the row below
   double pJx[NC];          // J^x of the row below
-  double pD[NC], pEps[NC]; // Type II denominators of the row below
+  double pD[NC], pEps[NC]; // denominators of the row below
   double pbx = 0.0, pby = 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) prevTopC[c] = prevJb[c] = pJx[c] = pD[c] = pEps[c] = 0.0;
@@ -387,41 +469,16 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1);
 
-    double ctr_r[NC], ctr_l[NC], ctr_t[NC], ctr_b[NC];
+    double ctr[NC][4];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double u0[9], u1[9], u2[9];
-      gather<K>(W, c, col, sl, sm, sh, u0, u1, u2);
-      double cf[23];
-      coeffs2d<K>(u0, u1, u2, cf, full);
-      if (!full) {
-#pragma unroll
-        for (int l = ncoef2d(K); l < 23; ++l) cf[l] = 0.0;
-      }
-      double E[MD + 1][4], O[MD + 1][3];
-      contract_y<NCF, MD>(cf, E, O);
-      // face centres: (+-1/2, 0) and (0, +-1/2)
-      double ev = 0.0, od = 0.0, tv = 0.0, bv = 0.0;
-#pragma unroll
-      for (int m = 0; m <= MD; ++m) {
-        if (m % 2 == 0) {
-          ev = fma(legn(m, 2), E[m][3], ev);
-          tv = fma(leg(m, 0.0), E[m][2] + O[m][2], tv);
-          bv = fma(leg(m, 0.0), E[m][2] - O[m][2], bv);
-        } else {
-          od = fma(legn(m, 2), E[m][3], od);
-        }
-      }
-      ctr_r[c] = ev + od;
-      ctr_l[c] = ev - od;
-      ctr_t[c] = tv;
-      ctr_b[c] = bv;
+      centre_values<K, FULL>(W, c, col, sl, sm, sh, ctr[c]);
+      FAM_SCHED_FENCE();
     }
 
-    // |jump| at the bottom face of this row (row below's top face)
     double Jb[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) Jb[c] = fabs(ctr_b[c] - prevTopC[c]);
+    for (int c = 0; c < NC; ++c) Jb[c] = fabs(ctr[c][3] - prevTopC[c]);
 
     // finish the row below
     if (r - 1 >= j0 && out_lane) {
@@ -438,7 +495,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
         sx = fmax(sx, sgx);
         sy = fmax(sy, sgy);
       }
-      const double delta = exp(-pbx * dt * sx / in.dx - pby * dt * sy / in.dy);
+      const double delta = exp(-pbx * cx * sx - pby * cy * sy);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         Uo[(c * 3 + 0) * in.plane + idx] = W.v[sl][c * 3 + 0][col];
@@ -451,14 +508,16 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     // this row: J^x, denominators and wave-speed bounds over the 3x3 patch
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double jl = ctr_l[c] - __shfl_up(ctr_r[c], 1, LANES);
+      const double jl = ctr[c][1] - __shfl_up(ctr[c][0], 1, LANES);
       const double jr = __shfl_down(jl, 1, LANES);
       pJx[c] = fabs(jl) + fabs(jr);
       prevJb[c] = Jb[c];
-      prevTopC[c] = ctr_t[c];
+      prevTopC[c] = ctr[c][2];
     }
     if (!ring_lo) {
       const int srow[3] = {sl, sm, sh};
+      const int cm = col > 0 ? col - 1 : 0, cp = col < LANES - 1 ? col + 1 : LANES - 1;
+      const int cc[3] = {cm, col, cp};
       double bx = 0.0, by = 0.0;
 #pragma unroll
       for (int b = 0; b < 3; ++b)
@@ -466,7 +525,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
         for (int a = 0; a < 3; ++a) {
           double avg[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) avg[c] = W.v[srow[b]][c * 3][col - 1 + a];
+          for (int c = 0; c < NC; ++c) avg[c] = W.v[srow[b]][c * 3][cc[a]];
           bx = fmax(bx, phys.speed(0, avg, bad));
           by = fmax(by, phys.speed(1, avg, bad));
         }
@@ -480,7 +539,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
           for (int b = 0; b < 3; ++b)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-              const double v = W.v[srow[b]][c * 3][col - 1 + a];
+              const double v = W.v[srow[b]][c * 3][cc[a]];
               S += v;
               mabs = fmax(mabs, fabs(v));
             }
@@ -488,7 +547,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
 #pragma unroll
           for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) D = fmax(D, fabs(W.v[srow[b]][c * 3][col - 1 + a] - S));
+            for (int a = 0; a < 3; ++a) D = fmax(D, fabs(W.v[srow[b]][c * 3][cc[a]] - S));
           pD[c] = D;
           pEps[c] = 1e-14 * fmax(mabs, 1.0);
         } else {
@@ -538,20 +597,20 @@ __device__ __forceinline__ void flush_wave_results(double amax_x, double amax_y,
 }
 
 template <int K, class P>
-__global__ void __launch_bounds__(LANES) stage2d_kernel(StageArgs A, Inst in, int H) {
+__global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
   double amx = 0.0, amy = 0.0;
   bool bad = false;
-  const int i0 = blockIdx.x * 62;
+  const int i0 = blockIdx.x * STRIP;
   const int j0 = blockIdx.y * H;
   stage_tile<K, P>(phys, A, in, i0, j0, H, W, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
 }
 
 template <int K, class P>
-__global__ void __launch_bounds__(LANES) stage2d_batched_kernel(StageArgs A, const Inst* __restrict__ insts,
+__global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* __restrict__ insts,
                                                                 const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
   const P phys = make_phys<P>(A.phys);
@@ -569,17 +628,20 @@ __global__ void __launch_bounds__(LANES) stage2d_batched_kernel(StageArgs A, con
 }
 
 template <int K, class P>
-__global__ void __launch_bounds__(LANES) oe2d_kernel(OEArgs A, Inst in, int H) {
+__global__ void FAM_OE_ATTR oe2d_kernel(OEArgs A, Inst in, int H) {
   __shared__ Window W;
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
-  oe_tile<K, P>(phys, A, in, blockIdx.x * 62, blockIdx.y * H, H, W, bad);
+  if (K == 6 && A.k6_table)
+    oe_tile<K, P, true>(phys, A, in, blockIdx.x * STRIP, blockIdx.y * H, H, W, bad);
+  else
+    oe_tile<K, P, false>(phys, A, in, blockIdx.x * STRIP, blockIdx.y * H, H, W, bad);
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
 
 template <int K, class P>
-__global__ void __launch_bounds__(LANES) oe2d_batched_kernel(OEArgs A, const Inst* __restrict__ insts,
+__global__ void FAM_OE_ATTR oe2d_batched_kernel(OEArgs A, const Inst* __restrict__ insts,
                                                              const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
   const P phys = make_phys<P>(A.phys);
@@ -589,7 +651,10 @@ __global__ void __launch_bounds__(LANES) oe2d_batched_kernel(OEArgs A, const Ins
     const int4 it = work[w];
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
-    oe_tile<K, P>(phys, A, in, it.y, it.z, it.w, W, bad);
+    if (K == 6 && A.k6_table)
+      oe_tile<K, P, true>(phys, A, in, it.y, it.z, it.w, W, bad);
+    else
+      oe_tile<K, P, false>(phys, A, in, it.y, it.z, it.w, W, bad);
   }
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
@@ -695,12 +760,12 @@ __global__ void type1_final_kernel(const double* __restrict__ dmax, Inst in, int
 // ---------------------------------------------------------------------------
 template <int K, class P>
 static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
-  dim3 grid((in.nx + 61) / 62, (in.ny + H - 1) / H);
+  dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
   hipLaunchKernelGGL((stage2d_kernel<K, P>), grid, dim3(LANES), 0, s, A, in, H);
 }
 template <int K, class P>
 static void launch_oe2d_t(const OEArgs& A, const Inst& in, int H, hipStream_t s) {
-  dim3 grid((in.nx + 61) / 62, (in.ny + H - 1) / H);
+  dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
   hipLaunchKernelGGL((oe2d_kernel<K, P>), grid, dim3(LANES), 0, s, A, in, H);
 }
 template <int K, class P>
