@@ -76,6 +76,12 @@ typedef struct {
   int k6_jump_from_table; /* k = 6, 2D: 0 = OE jumps of p_6 (the text's u_h^*),
                              1 = jumps of the full auxiliary Q_6, which is what
                              the printed matrices A_6, B_6, C_6 encode           */
+  int pp;                 /* 2D Euler only: positivity safeguard applied to each
+                             stage's reconstruction (the paper's auxiliary BP/PP
+                             limiter is cited, not specified; this is the scaling
+                             limiter toward the cell average that keeps density
+                             and pressure >= min(1e-13, rho_avg, p_avg) at all 32
+                             flux points of every cell).  0 = off.               */
 } fam_config;
 
 typedef struct fam_ctx fam_ctx;

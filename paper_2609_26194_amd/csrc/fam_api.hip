@@ -24,51 +24,11 @@
 #include <vector>
 
 #include "../../include/fam.h"
+#include "fam_ctx.h"
 #include "fam_kernels.h"
 
 using fam::Inst;
 using fam::StepState;
-
-struct fam_ctx {
-  std::vector<fam_config> cfg;
-  int ninst = 0;
-  int dim = 2, k = 5, sys = 2, nc = 4, nmom = 3, oe = 2, bcx = 0, bcy = 0, k6t = 0;
-  double gamma_k = 15.0;
-  fam::PhysParams phys{1.4, 1.0, 0.0};
-  hipStream_t stream = nullptr;
-  std::vector<size_t> offsets;
-  size_t len = 0, max_cells = 0;
-  double* W1 = nullptr;
-  double* W2 = nullptr;
-  StepState* st = nullptr;
-  int* flag = nullptr;
-  double* stats = nullptr;     // Type I: [inst*8 + ...]
-  double* partial = nullptr;   // Type I partial sums
-  double* dmax = nullptr;
-  int t1_blocks = 256;
-  int H = 32;                  // rows per strip tile (single instance)
-  // batched
-  Inst* d_insts[2][4] = {};    // [parity][stage 0..2, 3 = OE]
-  Inst* d_ainst[2] = {};       // [parity]: alpha_out = stage-0 input slot
-  int4* d_work = nullptr;
-  int nwork = 0;
-  int pblocks = 0;             // persistent grid size
-  std::vector<int> inst_H;
-  // graphs (keyed by U pointer, dt_fixed, t_final)
-  struct GKey {
-    double* U;
-    double dt_fixed, t_final;
-    bool operator<(const GKey& o) const {
-      if (U != o.U) return U < o.U;
-      if (dt_fixed != o.dt_fixed) return dt_fixed < o.dt_fixed;
-      return t_final < o.t_final;
-    }
-  };
-  std::map<GKey, hipGraphExec_t> graphs;
-  bool use_graph = true;
-  // adjoint scratch
-  void* adj = nullptr;
-};
 
 extern "C" const char* fam_status_str(fam_status s) {
   switch (s) {
@@ -98,6 +58,7 @@ static fam_status validate(const fam_config& c) {
   if (!(c.cfl > 0.0)) return FAM_ERR_ARG;
   if (c.system == FAM_EULER && !(c.gamma > 1.0)) return FAM_ERR_ARG;
   if ((size_t)c.nx * (size_t)(c.dim == 2 ? c.ny : 1) > ((size_t)1 << 31)) return FAM_ERR_ARG;
+  if (c.pp && !(c.system == FAM_EULER && c.dim == 2)) return FAM_ERR_ARG;
   return FAM_OK;
 }
 
@@ -121,7 +82,7 @@ static Inst make_inst(const fam_ctx* c, int i) {
   return in;
 }
 
-static Inst inst_for(const fam_ctx* c, int i, int parity, int stage) {
+Inst inst_for(const fam_ctx* c, int i, int parity, int stage) {
   Inst in = make_inst(c, i);
   StepState* s = c->st + i;
   if (stage < 3) {
@@ -175,7 +136,7 @@ static fam_status init_steps(fam_ctx* c) {
 }
 
 // per run: time, step count, termination and wave-speed slots back to zero
-static fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed) {
+fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed) {
   fam::launch_reset_steps(c->st, c->ninst, t_final, dt_fixed, c->stream);
   return FAM_OK;
 }
@@ -235,6 +196,7 @@ static void set_common(fam_ctx* c, const fam_config& f) {
   c->bcx = f.bc_x;
   c->bcy = f.bc_y;
   c->k6t = f.k6_jump_from_table;
+  c->pp = f.pp;
   c->gamma_k = f.oe_gamma_k > 0 ? f.oe_gamma_k : default_gamma_k(f.dim, f.k);
   c->phys = fam::PhysParams{f.gamma, f.ax, f.ay};
 }
@@ -277,7 +239,7 @@ extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_s
     const fam_config &a = per[0], &b = per[i];
     if (b.dim != 2 || b.k != a.k || b.system != a.system || b.gamma != a.gamma || b.oe != a.oe ||
         b.bc_x != a.bc_x || b.bc_y != a.bc_y || b.cfl != a.cfl || b.oe_gamma_k != a.oe_gamma_k ||
-        b.k6_jump_from_table != a.k6_jump_from_table || b.ax != a.ax || b.ay != a.ay)
+        b.k6_jump_from_table != a.k6_jump_from_table || b.ax != a.ax || b.ay != a.ay || b.pp != a.pp)
       return FAM_ERR_ARG;
   }
   if (per[0].oe == FAM_OE_TYPE1) return FAM_ERR_ARG;   // global statistics per instance: single contexts only
@@ -337,7 +299,7 @@ extern "C" int fam_num_instances(const fam_ctx* c) { return c ? c->ninst : 0; }
 // ---------------------------------------------------------------------------
 // enqueue helpers
 // ---------------------------------------------------------------------------
-static void enqueue_alpha_full(fam_ctx* c, const double* U, int parity) {
+void enqueue_alpha_full(fam_ctx* c, const double* U, int parity) {
   fam::launch_zero_alpha(c->st, c->ninst, parity, c->stream);
   if (c->dim == 1) {
     Inst in = inst_for(c, 0, parity, 0);
@@ -349,7 +311,7 @@ static void enqueue_alpha_full(fam_ctx* c, const double* U, int parity) {
   fam::launch_alpha2d(c->sys, c->phys, U, c->d_ainst[parity], c->ninst, c->max_cells, c->flag, c->stream);
 }
 
-static void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
+void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
                           const double* dt_override) {
   static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
   static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -362,6 +324,7 @@ static void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const
   A.cb = CB[s];
   A.flag = c->flag;
   A.done = &c->st[0].done;
+  A.pp = c->pp;
   if (c->ninst == 1) {
     Inst in = inst_for(c, 0, parity, s);
     if (dt_override) in.dt = dt_override;
@@ -374,7 +337,7 @@ static void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const
   }
 }
 
-static void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override) {
+void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override) {
   fam::OEArgs A{};
   A.phys = c->phys;
   A.Un = Un;
@@ -399,7 +362,7 @@ static void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, c
   }
 }
 
-static void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_final) {
+void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_final) {
   fam::launch_step_begin(c->st, c->ninst, parity, dt_fixed, t_final, c->stream);
   enqueue_stage(c, 0, parity, U, U, c->W1, nullptr);
   enqueue_stage(c, 1, parity, U, c->W1, c->W2, nullptr);

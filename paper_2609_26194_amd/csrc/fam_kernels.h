@@ -37,6 +37,7 @@ struct StageArgs {
   double ca, cb;           // Uout = ca U0 + cb (Us + dt R(Us))
   int* flag;
   const int* done;
+  int pp;                  // positivity limiter on the stage reconstruction (2D Euler)
 };
 
 struct OEArgs {

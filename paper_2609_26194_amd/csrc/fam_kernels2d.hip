@@ -154,9 +154,127 @@ __device__ __forceinline__ void gather(const Window& W, int c, int col, int sl, 
 }
 
 // ---------------------------------------------------------------------------
+// Optional positivity limiter (Euler): the reconstruction p is replaced by
+// avg + theta2 (w - avg), w = p with its density scaled by theta1 toward the
+// average, theta1 and theta2 the largest values keeping density and pressure
+// >= eps = min(1e-13, rho_avg, p(avg)) at all 32 flux points of the cell.
+// ---------------------------------------------------------------------------
+template <int NC>
+struct Limiter {
+  bool active = false;
+  double th1 = 1.0, th2 = 1.0;
+  double avg[NC];
+  __device__ __forceinline__ void apply(double* v) const {
+    if (!active) return;
+    const double r = avg[0] + th1 * (v[0] - avg[0]);
+    v[0] = avg[0] + th2 * (r - avg[0]);
+#pragma unroll
+    for (int c = 1; c < NC; ++c) v[c] = avg[c] + th2 * (v[c] - avg[c]);
+  }
+  template <int Q>
+  __device__ __forceinline__ void apply_col(double (&v)[NC][Q], int q) const {
+    double t[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) t[c] = v[c][q];
+    apply(t);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c][q] = t[c];
+  }
+};
+
+// smallest root in (0, 1] of a t^2 + b t + c (c > 0 and value <= 0 at t = 1), else 1
+__device__ __forceinline__ double smallest_root_unit(double a, double b, double c) {
+  const double disc = fmax(b * b - 4.0 * a * c, 0.0);
+  const double sq = sqrt(disc);
+  const double q = -0.5 * (b + (b >= 0.0 ? sq : -sq));
+  double r1 = (a == 0.0) ? 2.0 : q / a;
+  double r2 = c / (q == 0.0 ? 1.0 : q);
+  if (!(r1 > 0.0 && r1 <= 1.0)) r1 = 2.0;
+  if (!(r2 > 0.0 && r2 <= 1.0)) r2 = 2.0;
+  const double r = fmin(r1, r2);
+  return r > 1.0 ? 1.0 : r;
+}
+
+// the 32 flux points in 8 groups of 4: right, left, top, bottom faces, then the
+// volume rows eta = node(qy), qy = 0..3
+template <int MD>
+__device__ __forceinline__ double point_of_group(const double (&E)[MD + 1][4], const double (&O)[MD + 1][3],
+                                                 int grp, int q) {
+  if (grp == 0) return eval_pt<MD>(E, O, 2, 1.0, qnode(q), qsign(q));
+  if (grp == 1) return eval_pt<MD>(E, O, 2, -1.0, qnode(q), qsign(q));
+  if (grp == 2) return eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
+  if (grp == 3) return eval_pt<MD>(E, O, qnode(q), qsign(q), 2, -1.0);
+  const int qy = grp - 4;
+  return eval_pt<MD>(E, O, qnode(q), qsign(q), qnode(qy), qsign(qy));
+}
+
+template <int K, int NCF, int MD, class P>
+__device__ __forceinline__ void pp_limiter(const P& phys, const double (&cf)[P::NC][NCF], Limiter<P::NC>& L,
+                                           bool& bad) {
+  constexpr int NC = P::NC;
+  if constexpr (NC != 4) {
+    return;
+  } else {
+    const double g = phys.g;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) L.avg[c] = cf[c][0];
+    const double inv = 1.0 / L.avg[0];
+    const double pa = phys.pressure(L.avg, inv);
+    if (!(L.avg[0] > 0.0) || !(pa > 0.0)) {
+      bad = true;
+      return;
+    }
+    const double eps = fmin(fmin(L.avg[0], pa), 1e-13);
+    // pass 1: minimum density over the 32 flux points
+    double rmin = 1e300;
+    {
+      double E[MD + 1][4], O[MD + 1][3];
+      contract_y<NCF, MD>(cf[0], E, O);
+#pragma unroll
+      for (int g = 0; g < 8; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rmin = fmin(rmin, point_of_group<MD>(E, O, g, q));
+    }
+    double th1 = 1.0;
+    if (rmin < eps) th1 = (L.avg[0] - eps) / (L.avg[0] - rmin);
+    // pass 2: pressure along avg -> density-limited point values, 4 points at a time
+    const double kk = 2.0 / (g - 1.0);
+    const double rho0 = L.avg[0], m0 = L.avg[1], n0 = L.avg[2], E0 = L.avg[3];
+    const double qc = 2.0 * rho0 * E0 - (m0 * m0 + n0 * n0) - kk * eps * rho0;
+    double th2 = 1.0;
+#pragma unroll
+    for (int grp = 0; grp < 8; ++grp) {
+      double v[NC][4];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double E[MD + 1][4], O[MD + 1][3];
+        contract_y<NCF, MD>(cf[c], E, O);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[c][q] = point_of_group<MD>(E, O, grp, q);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double w0 = rho0 + th1 * (v[0][q] - rho0);
+        const double w[4] = {w0, v[1][q], v[2][q], v[3][q]};
+        const double pw = phys.pressure(w, 1.0 / w0);
+        if (pw < eps) {
+          const double rd = w0 - rho0, md = w[1] - m0, nd = w[2] - n0, Ed = w[3] - E0;
+          const double qa = 2.0 * rd * Ed - (md * md + nd * nd);
+          const double qb = 2.0 * (rho0 * Ed + rd * E0) - 2.0 * (m0 * md + n0 * nd) - kk * eps * rd;
+          th2 = fmin(th2, smallest_root_unit(qa, qb, qc));
+        }
+      }
+    }
+    L.th1 = th1;
+    L.th2 = th2;
+    L.active = (th1 < 1.0) || (th2 < 1.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // stage tile
 // ---------------------------------------------------------------------------
-template <int K, class P>
+template <int K, class P, bool PP>
 __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, int i0, int j0, int H,
                            Window& W, double& amax_x, double& amax_y, bool& bad) {
   constexpr int NC = P::NC;
@@ -222,6 +340,10 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       FAM_SCHED_FENCE();
     }
 
+    // optional positivity limiter on this cell's reconstruction
+    Limiter<NC> lim;
+    if constexpr (PP) pp_limiter<K, NCF, MD>(phys, cf, lim, bad);
+
     // bottom trace -> y-face flux below the current row: (i, r-1/2)
     double Gb[NC], Gt[NC];
 #pragma unroll
@@ -234,6 +356,10 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
         contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
         for (int q = 0; q < 4; ++q) bt[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, -1.0);
+      }
+      if constexpr (PP) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lim.apply_col(bt, q);
       }
       if (!ring_lo) {
 #pragma unroll
@@ -281,6 +407,10 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 #pragma unroll
       for (int q = 0; q < 4; ++q) prevTop[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
     }
+    if constexpr (PP) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lim.apply_col(prevTop, q);
+    }
 
     if (!ring_lo) {
       // x-face left of this lane: (i-1/2, r); left state = right trace of lane-1
@@ -297,6 +427,13 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
           for (int q = 0; q < 4; ++q) {
             rt[c][q] = eval_pt<MD>(E, O, 2, 1.0, qnode(q), qsign(q));
             lt[c][q] = eval_pt<MD>(E, O, 2, -1.0, qnode(q), qsign(q));
+          }
+        }
+        if constexpr (PP) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            lim.apply_col(rt, q);
+            lim.apply_col(lt, q);
           }
         }
 #pragma unroll
@@ -336,6 +473,10 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
           contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) vals[qq][c] = eval_pt<MD>(E, O, qnode(qq), qsign(qq), qnode(qy), qsign(qy));
+        }
+        if constexpr (PP) {
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) lim.apply(vals[qq]);
         }
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
@@ -596,7 +737,7 @@ __device__ __forceinline__ void flush_wave_results(double amax_x, double amax_y,
   }
 }
 
-template <int K, class P>
+template <int K, class P, bool PP>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
   if (*A.done) return;
@@ -605,11 +746,11 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   bool bad = false;
   const int i0 = blockIdx.x * STRIP;
   const int j0 = blockIdx.y * H;
-  stage_tile<K, P>(phys, A, in, i0, j0, H, W, amx, amy, bad);
+  stage_tile<K, P, PP>(phys, A, in, i0, j0, H, W, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
 }
 
-template <int K, class P>
+template <int K, class P, bool PP>
 __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* __restrict__ insts,
                                                                 const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
@@ -621,7 +762,7 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
     double amx = 0.0, amy = 0.0;
-    stage_tile<K, P>(phys, A, in, it.y, it.z, it.w, W, amx, amy, bad);
+    stage_tile<K, P, PP>(phys, A, in, it.y, it.z, it.w, W, amx, amy, bad);
     flush_wave_results(amx, amy, false, in.alpha_out, A.flag);
   }
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
@@ -761,7 +902,10 @@ __global__ void type1_final_kernel(const double* __restrict__ dmax, Inst in, int
 template <int K, class P>
 static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
-  hipLaunchKernelGGL((stage2d_kernel<K, P>), grid, dim3(LANES), 0, s, A, in, H);
+  if (A.pp)
+    hipLaunchKernelGGL((stage2d_kernel<K, P, true>), grid, dim3(LANES), 0, s, A, in, H);
+  else
+    hipLaunchKernelGGL((stage2d_kernel<K, P, false>), grid, dim3(LANES), 0, s, A, in, H);
 }
 template <int K, class P>
 static void launch_oe2d_t(const OEArgs& A, const Inst& in, int H, hipStream_t s) {
@@ -771,7 +915,12 @@ static void launch_oe2d_t(const OEArgs& A, const Inst& in, int H, hipStream_t s)
 template <int K, class P>
 static void launch_stage2d_b(const StageArgs& A, const Inst* insts, const int4* work, int nwork, int nblocks,
                              hipStream_t s) {
-  hipLaunchKernelGGL((stage2d_batched_kernel<K, P>), dim3(nblocks), dim3(LANES), 0, s, A, insts, work, nwork);
+  if (A.pp)
+    hipLaunchKernelGGL((stage2d_batched_kernel<K, P, true>), dim3(nblocks), dim3(LANES), 0, s, A, insts, work,
+                       nwork);
+  else
+    hipLaunchKernelGGL((stage2d_batched_kernel<K, P, false>), dim3(nblocks), dim3(LANES), 0, s, A, insts, work,
+                       nwork);
 }
 template <int K, class P>
 static void launch_oe2d_b(const OEArgs& A, const Inst* insts, const int4* work, int nwork, int nblocks,

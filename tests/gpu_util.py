@@ -12,9 +12,7 @@ def both_configs(**kw):
     """(oracle Config, library FamConfig) built from one set of keyword arguments."""
     from paper_2609_26194_amd import FamConfig
     ora = Config(**kw)
-    fam_kw = dict(kw)
-    fam_kw.pop("pp", None)
-    return ora, FamConfig(**fam_kw)
+    return ora, FamConfig(**kw)
 
 
 def to_dev(U):
