@@ -273,3 +273,27 @@ def density_wave_direction(n, rng, ny=None, gamma=1.4):
     d[2] = 0.5 * drho
     d[3] = 0.25 * drho
     return d
+
+
+def smooth_density_wave_direction(n, rng, ny=None):
+    """A random smooth perturbation of the density-wave state keeping u = v = 1/2, p = 1.
+
+    d(rho) = sum_{m=1..4} b_m sin(2 pi k_m . x + phi_m) with b_m ~ N(0, 1),
+    k_m integer vectors in [-3,3]^2 minus 0 and phi_m ~ U[0, 2 pi), as exact cell
+    moments; d(rho u) = d(rho v) = d(rho)/2 and dE = d(rho)/4 as for
+    ``density_wave_direction``.  Being smooth, it changes the interface jumps of
+    the reconstruction only at the truncation-error level.
+    """
+    ny = n if ny is None else ny
+    b = rng.standard_normal(4)
+    ks = []
+    while len(ks) < 4:
+        kv = rng.integers(-3, 4, size=2)
+        if kv[0] != 0 or kv[1] != 0:
+            ks.append((int(kv[0]), int(kv[1])))
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=4)
+
+    def f(X, Y):
+        drho = sum(b[m] * np.sin(2.0 * math.pi * (ks[m][0] * X + ks[m][1] * Y) + phi[m]) for m in range(4))
+        return np.stack([drho, 0.5 * drho, 0.5 * drho, 0.25 * drho])
+    return moments_2d(f, 0.0, 1.0, 0.0, 1.0, n, ny)

@@ -161,7 +161,7 @@ static fam_status build_inst_tables(fam_ctx* c) {
 }
 
 static void destroy_graphs(fam_ctx* c) {
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
 }
 
@@ -169,20 +169,17 @@ void fam_adjoint_free(fam_ctx* c);
 
 extern "C" void fam_destroy(fam_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   fam_adjoint_free(c);
-  hipFree(c->W1);
-  hipFree(c->W2);
-  hipFree(c->st);
-  hipFree(c->flag);
-  hipFree(c->stats);
-  hipFree(c->partial);
-  hipFree(c->dmax);
+  void* bufs[] = {c->W1, c->W2, c->st, c->flag, c->stats, c->partial, c->dmax, c->d_work};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
   for (auto& a : c->d_insts)
-    for (auto* p : a) hipFree(p);
-  for (auto* p : c->d_ainst) hipFree(p);
-  hipFree(c->d_work);
+    for (auto* p : a)
+      if (p) (void)hipFree(p);
+  for (auto* p : c->d_ainst)
+    if (p) (void)hipFree(p);
   delete c;
 }
 
@@ -447,7 +444,7 @@ static fam_status get_graph(fam_ctx* c, double* U, double dt_fixed, double t_fin
   HIP_TRY(hipStreamEndCapture(c->stream, &g));
   hipGraphExec_t ex;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return FAM_ERR_DEVICE;
   c->graphs[key] = ex;
   *out = ex;

@@ -30,6 +30,7 @@
 #include <utility>
 
 #include "fam_device.h"
+#include "fam_eval.h"
 #include "fam_kernels.h"
 
 namespace fam {
@@ -54,56 +55,6 @@ namespace fam {
 
 constexpr int LANES = 64;
 constexpr int NPL = 12;            // planes held in LDS for up to 4 components x 3 moments
-
-// Gauss node q = 0..3 at -GS1, -GS0, +GS0, +GS1
-__device__ __forceinline__ constexpr int qnode(int q) { return (q == 0 || q == 3) ? 1 : 0; }
-__device__ __forceinline__ constexpr double qsign(int q) { return q < 2 ? -1.0 : 1.0; }
-__device__ __forceinline__ constexpr double qw(int q) { return (q == 0 || q == 3) ? GW1 : GW0; }
-__device__ __forceinline__ constexpr double qx(int q) {
-  return q == 0 ? -GS1 : q == 1 ? -GS0 : q == 2 ? GS0 : GS1;
-}
-
-// even / odd partial contractions over the y-degree: E[m][w], O[m][w] at
-// w = 0 (GS0), 1 (GS1), 2 (1/2), 3 (0; even part only)
-template <int NCF, int MD>
-__device__ __forceinline__ void contract_y(const double* c, double (&E)[MD + 1][4],
-                                           double (&O)[MD + 1][3]) {
-#pragma unroll
-  for (int m = 0; m <= MD; ++m) {
-#pragma unroll
-    for (int w = 0; w < 4; ++w) E[m][w] = 0.0;
-#pragma unroll
-    for (int w = 0; w < 3; ++w) O[m][w] = 0.0;
-  }
-#pragma unroll
-  for (int l = 0; l < NCF; ++l) {
-    const int m = AX[l], b = AY[l];
-    if (b % 2 == 0) {
-#pragma unroll
-      for (int w = 0; w < 3; ++w) E[m][w] = fma(c[l], legn(b, w), E[m][w]);
-      E[m][3] = fma(c[l], leg(b, 0.0), E[m][3]);
-    } else {
-#pragma unroll
-      for (int w = 0; w < 3; ++w) O[m][w] = fma(c[l], legn(b, w), O[m][w]);
-    }
-  }
-}
-
-// p(xi, eta) with xi = sx * node(gx), eta = sy * node(gy); node 2 = 1/2
-template <int MD>
-__device__ __forceinline__ double eval_pt(const double (&E)[MD + 1][4], const double (&O)[MD + 1][3],
-                                          int gx, double sx, int gy, double sy) {
-  double ev = 0.0, od = 0.0;
-#pragma unroll
-  for (int m = 0; m <= MD; ++m) {
-    const double Qm = E[m][gy] + sy * O[m][gy];
-    if (m % 2 == 0)
-      ev = fma(legn(m, gx), Qm, ev);
-    else
-      od = fma(legn(m, gx), Qm, od);
-  }
-  return ev + sx * od;
-}
 
 // ---------------------------------------------------------------------------
 // LDS row window: lane l holds LDS column l = grid column i0 - 2 + l.  Lanes 0
@@ -508,51 +459,9 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 
 // ---------------------------------------------------------------------------
 // OE tile.  The four face-centre values of a cell's reconstruction, p(+-1/2, 0)
-// and p(0, +-1/2), are fixed linear functionals of its 3x3 stencil moments; their
-// weights are evaluated at compile time from the same coefficient formulas.
+// and p(0, +-1/2), are fixed linear functionals of its 3x3 stencil moments
+// (weights in fam_eval.h, folded at compile time).
 // ---------------------------------------------------------------------------
-struct CentreWeights {
-  double w[4][27];   // [r, l, t, b][u0 1..9, u1 1..9, u2 1..9]
-};
-
-template <int K, bool FULL>
-__host__ __device__ constexpr CentreWeights make_centre_weights() {
-  CentreWeights cw{};
-  const double px[4] = {0.5, -0.5, 0.0, 0.0}, py[4] = {0.0, 0.0, 0.5, -0.5};
-  const int ncf = FULL ? 23 : ncoef2d(K);
-  for (int in = 0; in < 27; ++in) {
-    double u[27] = {};
-    u[in] = 1.0;
-    double c[23] = {};
-    coeffs2d<K>(u, u + 9, u + 18, c, FULL);
-    for (int f = 0; f < 4; ++f) {
-      double v = 0.0;
-      for (int l = 0; l < ncf; ++l) v += c[l] * leg(AX[l], px[f]) * leg(AY[l], py[f]);
-      cw.w[f][in] = v;
-    }
-  }
-  return cw;
-}
-
-template <int K, bool FULL>
-struct CentreTable {
-  static constexpr CentreWeights t = make_centre_weights<K, FULL>();
-};
-
-// v += w * u[I] with w a compile-time constant (skipped when zero)
-template <int K, bool FULL, int F, int I>
-__device__ __forceinline__ void centre_acc(double& v, const double (&u)[27]) {
-  constexpr double w = CentreTable<K, FULL>::t.w[F][I];
-  if constexpr (w != 0.0) v = fma(w, u[I], v);
-}
-
-template <int K, bool FULL, int F, int... I>
-__device__ __forceinline__ double centre_dot(const double (&u)[27], std::integer_sequence<int, I...>) {
-  double v = 0.0;
-  (centre_acc<K, FULL, F, I>(v, u), ...);
-  return v;
-}
-
 template <int K, bool FULL>
 __device__ __forceinline__ void centre_values(const Window& W, int c, int col, int sl, int sm, int sh,
                                               double (&out)[4]) {
