@@ -1,18 +1,32 @@
 """Benchmark of the FAM step on one MI355X.
 
-Workload: 2D Euler (gamma = 1.4), 2048 x 2048 cells on [0,1]^2, FAM k = 5, FP64,
-four-quadrant piecewise-constant data drawn from seed 0 (rho ~ U[0.1,1.5],
+Main workload: 2D Euler (gamma = 1.4), 2048 x 2048 cells on [0,1]^2, FAM k = 5,
+FP64, four-quadrant piecewise-constant data drawn from seed 0 (rho ~ U[0.1,1.5],
 u, v ~ U[-1,1], p ~ U[0.02,1.5] per quadrant), transmissive boundaries, CFL 0.2,
-OE Type II.  A step is the whole hot path: time step from the wave speeds,
-three SSP-RK3 stages (reconstruction, Lax-Friedrichs flux, volume quadrature,
+OE Type II, positivity limiter on (without it this data leaves the admissible
+set within 60-70 steps at k = 5; the limiter is the identity in every cell whose
+flux points are all admissible).  A step is the whole hot path: time step from the wave speeds, three
+SSP-RK3 stages (reconstruction, Lax-Friedrichs flux, volume quadrature,
 Shu-Osher update) and the OE pass.  Steps run through fam_run (replayed HIP
 graphs), inputs resident in HBM before the timed region.
 
-Prints one JSON line: the metric (cell-updates/s), a roofline object for the
-dominant kernel (the RK stage kernel; its launches are timed with HIP events on
-the library's own stream) and the oracle's CPU throughput on a bounded sample.
+Prints one JSON line with the metric (cell-updates/s), a roofline object for the
+dominant kernel (the RK stage kernel, its launches timed with HIP events on the
+library's own stream), the oracle's CPU throughput on a bounded sample, and two
+sub-measurements: the batched workload (256 uneven instances in one persistent
+launch per stage against one context per instance) and the adjoint workload
+(gradient cost over forward cost at 1024^2, 400 steps, checkpoint every 20).
+
+``python bench.py --ingest-counters FETCH.csv WRITE.csv`` turns the per-dispatch
+CSVs of two ``rocprofv3 --pmc`` runs of this script (FETCH_SIZE, then
+WRITE_SIZE) into profiles/stage2d_k5_2048_counters.json: HBM bytes per stage
+launch, scaled by what the same counters read for the 1 GiB streaming copy this
+script performs, with a hash of the stage kernel's sources so that the figure is
+dropped (traffic null) once the kernel changes.
 """
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -25,7 +39,10 @@ sys.path.insert(0, ROOT)
 # doubles) and writes Uout (12); stages 1, 2 also read U0 (12)
 STAGE_BYTES = {0: 24 * 8, 1: 36 * 8, 2: 36 * 8}
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6          # 256 CUs x 2.4 GHz x 128 FP64 flops / clock
+COPY_BYTES = 1 << 30             # calibration copy for the HBM counters
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "stage2d_k5_2048_counters.json")
+STAGE_SOURCES = ["fam_kernels2d.hip", "fam_device.h", "fam_eval.h", "fam_kernels.h"]
 
 
 def parse():
@@ -36,17 +53,91 @@ def parse():
     p.add_argument("--n", type=int, default=2048)
     p.add_argument("--k", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-n", type=int, default=256)
-    p.add_argument("--cpu-sample-steps", type=int, default=12)
+    p.add_argument("--cpu-sample-n", type=int, default=512)
+    p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--batched-steps", type=int, default=100)
+    p.add_argument("--no-adjoint", action="store_true")
+    p.add_argument("--adjoint-n", type=int, default=1024)
+    p.add_argument("--adjoint-steps", type=int, default=400)
+    p.add_argument("--adjoint-checkpoint", type=int, default=20)
+    p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     return p.parse_args()
 
 
-def stage_flops_per_cell(k):
-    """Algorithmic FP64 operations of R(U) + update per cell."""
-    from paper_2609_26194_amd.opcount import stage_flops
-    return stage_flops(k)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def stage_sources_hash():
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_26194_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+# ---------------------------------------------------------------------------
+# HBM counters
+# ---------------------------------------------------------------------------
+def _per_dispatch(path, counter):
+    """{kernel name: [value per dispatch]} from a rocprofv3 counter_collection CSV."""
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def ingest_counters(fetch_csv, write_csv):
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+
+    def pick(d, key):
+        names = [n for n in d if key in n]
+        if not names:
+            raise SystemExit(f"no dispatch of a kernel matching {key!r}")
+        return [v for n in names for v in d[n]]
+
+    stage_f = pick(fetch, "stage2d_kernel<5")
+    stage_w = pick(write, "stage2d_kernel<5")
+    copy_f = max(pick(fetch, "Mul"))
+    copy_w = max(pick(write, "Mul"))
+    kib = COPY_BYTES / 1024.0
+    f_scale, w_scale = kib / copy_f, kib / copy_w
+    fetch_b = sum(stage_f) / len(stage_f) * 1024.0 * f_scale
+    write_b = sum(stage_w) / len(stage_w) * 1024.0 * w_scale
+    rec = {"kernel": "stage2d_kernel<5, Euler<2>, true> (all three RK stages)",
+           "workload": "2D Euler four-quadrant 2048x2048, k=5, positivity limiter",
+           "dispatches": len(stage_f),
+           "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+           "traffic_bytes_per_launch": fetch_b + write_b,
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": copy_f, "write_kib": copy_w,
+                                "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernel_sources_sha256": stage_sources_hash()}
+    os.makedirs(os.path.dirname(COUNTERS_JSON), exist_ok=True)
+    with open(COUNTERS_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+def stored_traffic():
+    """HBM bytes per stage launch from the committed counters, or None if stale."""
+    try:
+        with open(COUNTERS_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != stage_sources_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# measurements
+# ---------------------------------------------------------------------------
 def cpu_baseline(n, steps):
     """The oracle as it stands, on the same recipe at n x n for `steps` steps."""
     import torch
@@ -54,7 +145,7 @@ def cpu_baseline(n, steps):
     from oracle.scheme import Config, step
     threads = torch.get_num_threads()
     cfg = Config(dim=2, nx=n, ny=n, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
-                 oe="type2", cfl=0.2)
+                 oe="type2", cfl=0.2, pp=True)
     U = torch.tensor(fi.four_quadrant(n, 0))
     U, _ = step(U, cfg)  # warm-up
     t0 = time.perf_counter()
@@ -62,54 +153,24 @@ def cpu_baseline(n, steps):
         U, _ = step(U, cfg)
     dt = time.perf_counter() - t0
     return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n}x{n} cells of the same workload recipe, {steps} steps ({dt:.1f} s)"}
+            "sample": f"{n}x{n} cells of the same workload recipe, {steps} steps after one warm-up step "
+                      f"({dt:.1f} s)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
-              file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
+def stage_roofline(fam, U, k, cells, reps=10):
+    """Per-launch duration of the three RK stage launches, HIP events on the library stream."""
     import torch
-    import fam_inputs as fi
-    from paper_2609_26194_amd import Fam, FamConfig
-
-    n, k = args.n, args.k
-    cfg = FamConfig(dim=2, nx=n, ny=n, k=k, system="euler", bc_x="transmissive", bc_y="transmissive",
-                    oe="type2", cfl=0.2)
-    U0 = torch.tensor(fi.four_quadrant(n, 0), dtype=torch.float64).cuda()
-    fam = Fam(cfg)
-    U = U0.clone()
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    if args.warmup:
-        fam.run(U, 0.0, args.warmup)
-    U.copy_(U0)
-    torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    steps, t_sim = fam.run(U, 0.0, args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    cells = n * n
-    value = cells * steps / elapsed
-
-    # dominant kernel: the RK stage kernel, timed per launch with HIP events on
-    # the library's stream, same launch configuration as inside the steps
+    from paper_2609_26194_amd.fam import fam_stage
     dtd = fam.dt(U)
     W1, W2 = torch.empty_like(U), torch.empty_like(U)
-    reps = 10
-    durs = {0: [], 1: [], 2: []}
     ins = {0: (U, U, W1), 1: (U, W1, W2), 2: (U, W2, W1)}
+    durs = {0: [], 1: [], 2: []}
     for rep in range(reps + 1):
-        fam.dt(U)
         for s in range(3):
             U0_, Us_, Uo_ = ins[s]
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             fam.stream.wait_stream(torch.cuda.current_stream())
             e0.record(fam.stream)
-            from paper_2609_26194_amd.fam import fam_stage
             fam_stage(fam.h, s, U0_, Us_, Uo_, dtd)
             e1.record(fam.stream)
             torch.cuda.current_stream().wait_stream(fam.stream)
@@ -117,19 +178,156 @@ def main():
             if rep > 0:
                 durs[s].append(e0.elapsed_time(e1) * 1e-3)
     avg = {s: sum(v) / len(v) for s, v in durs.items()}
-    # stage 1 (the middle stage) is the representative launch: reads Us and U0, writes Uout
-    dur = avg[1]
-    flops = stage_flops_per_cell(k) * cells
-    achieved_tflops = flops / dur / 1e12
-    bytes_alg = STAGE_BYTES[1] * cells
-    achieved_gbs = bytes_alg / dur / 1e9
-    roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None,
-                "kernel": "stage2d_kernel<5, Euler<2>> (RK stage 2 of 3)",
-                "launch_ms": dur * 1e3, "hbm_algorithmic_GBs": achieved_gbs,
-                "hbm_algorithmic_frac": achieved_gbs / HBM_PEAK_GBS,
-                "stage_launch_ms": [avg[0] * 1e3, avg[1] * 1e3, avg[2] * 1e3]}
-    step_bytes = 928 * cells
+    dur = sum(avg.values()) / 3.0
+    from paper_2609_26194_amd.opcount import stage_flops
+    achieved = stage_flops(k) * cells / dur / 1e12
+    bytes_alg = sum(STAGE_BYTES.values()) / 3.0 * cells
+    gbs = bytes_alg / dur / 1e9
+    traffic = stored_traffic()
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": f"stage2d_kernel<{k}, Euler<2>, true> (mean of the three RK stage launches)",
+            "launch_ms": dur * 1e3, "stage_launch_ms": [avg[s] * 1e3 for s in range(3)],
+            "flops_per_cell": stage_flops(k), "algorithmic_bytes_per_launch": bytes_alg,
+            "hbm_algorithmic_GBs": gbs, "hbm_algorithmic_frac": gbs / HBM_PEAK_GBS}
+
+
+def copy_calibration():
+    """One plain streaming kernel that reads COPY_BYTES and writes COPY_BYTES (y = 1.0 * x),
+    the HBM-counter calibration.  The buffers exceed the 256 MB last-level cache and a
+    512 MiB fill runs in between, so the read comes from HBM."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    flush = torch.empty(512 << 17, dtype=torch.float64, device="cuda")
+    flush.fill_(0.0)
+    torch.cuda.synchronize()
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    del flush
+
+
+def batched(steps):
+    """Batched workload: 256 square instances (sizes from seed 1, data seeds 1000 + i), k = 5,
+    OE Type II, positivity limiter on, transmissive; one persistent launch per stage against
+    one context per instance."""
+    import torch
+    import fam_inputs as fi
+    from paper_2609_26194_amd import Fam, FamConfig
+    sizes = fi.batch_sizes(256, 1)
+    cfgs = [FamConfig(dim=2, nx=n, ny=n, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
+                      oe="type2", cfl=0.2, pp=True) for n in sizes]
+    cells = sum(n * n for n in sizes)
+    states = [torch.tensor(fi.batch_instance(i, n), dtype=torch.float64).cuda() for i, n in enumerate(sizes)]
+    bat = Fam(cfgs[0], batch=cfgs)
+    offs = bat.offsets()
+    U0 = torch.zeros(bat.len, dtype=torch.float64, device="cuda")
+    for o, s in zip(offs, states):
+        U0[o:o + s.numel()] = s.reshape(-1)
+    tuned = bat.autotune(U0)
+    U = U0.clone()
+    bat.run(U, 0.0, 4)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat.run(U, 0.0, steps)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    bat.close()
+    # one context per instance, each advanced with its own graph-replayed fam_run
+    singles = [Fam(c) for c in cfgs]
+    work = [s.clone() for s in states]
+    for f, w in zip(singles, work):
+        f.autotune(w, reps=2)
+        f.run(w, 0.0, 4)
+    for w, s in zip(work, states):
+        w.copy_(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f, w in zip(singles, work):
+        f.run(w, 0.0, steps)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    same = all(torch.equal(U[o:o + w.numel()], w.reshape(-1)) for o, w in zip(offs, work))
+    for f in singles:
+        f.close()
+    return {"workload": "256 instances, sizes U{64..512} (seed 1), four-quadrant data (seeds 1000+i), "
+                        f"k=5, OE Type II, positivity limiter, {steps} steps",
+            "cells": cells, "batched_cell_updates_per_s": cells * steps / t_b,
+            "per_instance_cell_updates_per_s": cells * steps / t_s,
+            "speedup": t_s / t_b, "batched_ms_per_step": t_b / steps * 1e3,
+            "per_instance_ms_per_step": t_s / steps * 1e3, "bitwise_equal": bool(same),
+            "autotuned": {"tile_height": tuned[0], "persistent_blocks": tuned[1]}}
+
+
+def adjoint(n, steps, every):
+    """Adjoint workload: periodic density waves (seed 2) on n x n, k = 5, OE Type II,
+    fixed dt = half the CFL step of the initial state; gradient of the window functional."""
+    import torch
+    import fam_inputs as fi
+    from paper_2609_26194_amd import Fam, FamConfig
+    cfg = FamConfig(dim=2, nx=n, ny=n, k=5, system="euler", bc_x="periodic", bc_y="periodic",
+                    oe="type2", cfl=0.2)
+    fam = Fam(cfg)
+    U0 = torch.tensor(fi.density_waves(n), dtype=torch.float64).cuda()
+    fam.autotune(U0)
+    dt = 0.5 * float(fam.dt(U0)[0])
+    U = U0.clone()
+    fam.run(U, 0.0, 10, dt)
+    fam.adjoint(U0, every, dt, every)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fam.run(U, 0.0, steps, dt)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J, g = fam.adjoint(U0, steps, dt, every)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter() - t0
+    fam.close()
+    return {"workload": f"2D Euler periodic density waves (seed 2) {n}x{n}, k=5, OE Type II, {steps} steps, "
+                        f"checkpoint every {every}", "J": J,
+            "forward_ms": t_f * 1e3, "gradient_ms": t_a * 1e3, "gradient_over_forward": t_a / t_f}
+
+
+def main():
+    args = parse()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import fam_inputs as fi
+    from paper_2609_26194_amd import Fam, FamConfig
+
+    n, k = args.n, args.k
+    cfg = FamConfig(dim=2, nx=n, ny=n, k=k, system="euler", bc_x="transmissive", bc_y="transmissive",
+                    oe="type2", cfl=0.2, pp=True)
+    U0 = torch.tensor(fi.four_quadrant(n, 0), dtype=torch.float64).cuda()
+    fam = Fam(cfg)
+    tuned = fam.autotune(U0)
+    log(f"autotuned strip-tile heights: stage {tuned[0]}, OE {tuned[1]}")
+    U = U0.clone()
+    log(f"warmup {args.warmup} steps")
+    if args.warmup:
+        fam.run(U, 0.0, args.warmup)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    steps, t_sim = fam.run(U, 0.0, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cells = n * n
+    value = cells * steps / elapsed
+    log("stage launches")
+    roofline = stage_roofline(fam, U, k, cells)
+    fam.close()
+    copy_calibration()
     out = {
         "metric": "2D Euler FAM cell-updates/s (FP64, k=5)",
         "value": value,
@@ -144,14 +342,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"2D Euler four-quadrant (seed 0) {n}x{n}, FAM k={k}, OE Type II, "
-                               f"transmissive, CFL 0.2", "cells": cells, "k": k,
-                   "step_algorithmic_GBs": step_bytes * steps / elapsed / 1e9},
+                               f"transmissive, CFL 0.2, positivity limiter", "cells": cells, "k": k, "t_simulated": t_sim,
+                   "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}},
         "roofline": roofline,
     }
+    if not args.no_batched:
+        log("batched workload")
+        out["batched"] = batched(args.batched_steps)
+    if not args.no_adjoint:
+        log("adjoint workload")
+        out["adjoint"] = adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_checkpoint)
     if not args.no_cpu_baseline:
-        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        log("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps)
-    fam.close()
     print(json.dumps(out))
 
 

@@ -184,17 +184,42 @@ def draw_density_waves(seed):
     return a, ks
 
 
+def _sincos_moments_1d(k, n):
+    """Cell average and scaled first moment of sin(2 pi k x), cos(2 pi k x) on n cells of [0,1]."""
+    q, w = _gauss()
+    X = (np.arange(n) + 0.5)[:, None] / n + q[None, :] / n
+    s, c = np.sin(2.0 * math.pi * k * X), np.cos(2.0 * math.pi * k * X)
+    return s @ w, s @ (w * q), c @ w, c @ (w * q)
+
+
 def density_waves(n, seed=2, gamma=1.4, ny=None):
-    """rho = 1 + 0.2 sum_m a_m sin(2 pi k_m . x), u = v = 1/2, p = 1 on periodic [0,1]^2."""
+    """rho = 1 + 0.2 sum_m a_m sin(2 pi k_m . x), u = v = 1/2, p = 1 on periodic [0,1]^2.
+
+    Exact moments by the same Gauss rule as ``moments_2d``, evaluated in separable
+    form: sin(a + b) = sin a cos b + cos a sin b, so each cell moment of a mode is a
+    sum of products of 1D cell moments.  The state is linear in rho on this
+    family: rho u = rho v = rho / 2 and E = p / (gamma - 1) + rho / 4.
+    """
     a, ks = draw_density_waves(seed)
     ny = n if ny is None else ny
-
-    def f(X, Y):
-        rho = 1.0 + 0.2 * sum(a[m] * np.sin(2.0 * math.pi * (ks[m][0] * X + ks[m][1] * Y))
-                              for m in range(4))
-        half = np.full_like(rho, 0.5)
-        return euler_conservative(rho, half, np.ones_like(rho), half, gamma)
-    return moments_2d(f, 0.0, 1.0, 0.0, 1.0, n, ny)
+    r0 = np.ones((ny, n))
+    r1 = np.zeros((ny, n))
+    r2 = np.zeros((ny, n))
+    for m in range(4):
+        sx0, sx1, cx0, cx1 = _sincos_moments_1d(ks[m][0], n)
+        sy0, sy1, cy0, cy1 = _sincos_moments_1d(ks[m][1], ny)
+        amp = 0.2 * a[m]
+        r0 = r0 + amp * (cy0[:, None] * sx0[None, :] + sy0[:, None] * cx0[None, :])
+        r1 = r1 + amp * (cy0[:, None] * sx1[None, :] + sy0[:, None] * cx1[None, :])
+        r2 = r2 + amp * (cy1[:, None] * sx0[None, :] + sy1[:, None] * cx0[None, :])
+    rho = np.stack([r0, r1, r2])
+    U = np.empty((4, 3, ny, n))
+    U[0] = rho
+    U[1] = 0.5 * rho
+    U[2] = 0.5 * rho
+    U[3] = 0.25 * rho
+    U[3, 0] += 1.0 / (gamma - 1.0)
+    return U
 
 
 def smooth_euler_1d(n, gamma=1.4):

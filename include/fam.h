@@ -133,6 +133,18 @@ fam_status fam_oe(fam_ctx* ctx, const double* Un, double* Uout, const double* dt
  * clears the flag. */
 fam_status fam_check(fam_ctx* ctx);
 
+/* Launch-shape autotuner (not part of the method: it only picks how the same
+ * arithmetic is tiled).  Times candidate shapes on the state U (device, read
+ * only) with reps timed launches each and keeps the fastest for this context:
+ * a single 2D instance tunes the strip-tile height of the RK stage kernel and of
+ * the OE kernel separately; a batch tunes the tile height of its work list and
+ * the persistent grid size.  Results are unchanged by the choice (bitwise).
+ * The context's stage buffers are overwritten, captured step graphs are
+ * dropped, and the device flag is cleared.  choice (host, may be NULL, 2 ints)
+ * receives (stage H, OE H) or (batch H, persistent blocks).  Synchronous.
+ * FAM_ERR_ARG for a NULL context / state or reps < 1; 1D contexts: no-op. */
+fam_status fam_autotune(fam_ctx* ctx, const double* U, int reps, int* choice);
+
 /* Gradient of a final-time functional J(U_T) with respect to the initial state
  * U0 after nsteps steps with the fixed time step dt (not differentiated), by
  * hand-written adjoint kernels of the OE, the three RK stages and R(U), with a

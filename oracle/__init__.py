@@ -19,9 +19,13 @@ The oracle is plain, slow and written from the paper's definitions:
                        oracle's own step.
 
 All floating-point work is FP64 (torch CPU tensors).  Where the paper is silent
-or ambiguous the oracle takes one documented reading (wave speed of the Rusanov
-flux evaluated pointwise from both traces; transmissive ghosts copy every
-moment; the k = 6 two-dimensional OE jumps use p_6 by default).
+or ambiguous the oracle takes one documented reading (one Lax-Friedrichs wave
+speed per direction and stage: the maximum spectral radius over the cell
+averages of the stage state; transmissive ghosts copy every moment; the k = 6
+two-dimensional OE jumps use p_6 by default).  The optional positivity limiter
+(``Config.pp``) is this project's design of the standard safeguard the paper
+cites without stating it; it is pinned by invariants (identity on admissible
+data, admissible and average-preserving output, tightness of the scaling).
 """
 from .physics import NonPhysicalState, gauss4  # noqa: F401
 from .scheme import Config, cfl_dt, oe, residual, rk3, rk3_stage, run, step  # noqa: F401

@@ -351,57 +351,106 @@ __global__ void adj_axpy_kernel(size_t n, double a, const double* __restrict__ x
 // ---------------------------------------------------------------------------
 // (3) alpha: argmax of the spectral radii at the averages and its route
 // ---------------------------------------------------------------------------
-__global__ void adj_alpha_init_kernel(double* smax, int* sidx) {
-  if (threadIdx.x < 2) {
-    smax[threadIdx.x] = 0.0;
-    sidx[threadIdx.x] = INT_MAX;
+constexpr int ALPHA_BLOCKS = 1024;   // partials of the argmax pass
+constexpr int RED_T = 1024;          // threads of the single-block final reductions
+
+// (v, i) pairs: larger v wins, equal v -> smaller i (first maximal cell)
+__device__ __forceinline__ void argmax_merge(double& v, int& i, double v2, int i2) {
+  if (v2 > v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
   }
 }
 
-__global__ void __launch_bounds__(256) adj_alpha_max_kernel(AdjMesh m, const double* __restrict__ U, double* smax) {
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) argmax_merge(v, i, __shfl_xor(v, off, 64), __shfl_xor(i, off, 64));
+}
+
+// block partials of (max speed, first argmax) in x and y
+__global__ void __launch_bounds__(256) adj_alpha_part_kernel(AdjMesh m, const double* __restrict__ U,
+                                                             double* __restrict__ pv, int* __restrict__ pi) {
+  __shared__ double sv[2][4];
+  __shared__ int si[2][4];
   const Euler<2> ph{m.gamma};
-  double mx = 0.0, my = 0.0;
   bool bad = false;
+  double vx = -1.0, vy = -1.0;
+  int ix = INT_MAX, iy = INT_MAX;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < m.plane; k += (size_t)gridDim.x * blockDim.x) {
     double a[4] = {U[k], U[3 * m.plane + k], U[6 * m.plane + k], U[9 * m.plane + k]};
-    mx = fmax(mx, ph.speed(0, a, bad));
-    my = fmax(my, ph.speed(1, a, bad));
+    argmax_merge(vx, ix, ph.speed(0, a, bad), (int)k);
+    argmax_merge(vy, iy, ph.speed(1, a, bad), (int)k);
   }
-  mx = wave_max(mx);
-  my = wave_max(my);
+  wave_argmax(vx, ix);
+  wave_argmax(vy, iy);
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomic_max_nonneg(&smax[0], mx);
-    atomic_max_nonneg(&smax[1], my);
+    sv[0][w] = vx; si[0][w] = ix;
+    sv[1][w] = vy; si[1][w] = iy;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int d = threadIdx.x;
+    double v = sv[d][0];
+    int i = si[d][0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) argmax_merge(v, i, sv[d][q], si[d][q]);
+    pv[2 * blockIdx.x + d] = v;
+    pi[2 * blockIdx.x + d] = i;
   }
 }
 
-__global__ void __launch_bounds__(256) adj_alpha_arg_kernel(AdjMesh m, const double* __restrict__ U,
-                                                            const double* smax, int* sidx) {
-  const Euler<2> ph{m.gamma};
-  bool bad = false;
-  const double tx = smax[0], ty = smax[1];
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < m.plane; k += (size_t)gridDim.x * blockDim.x) {
-    double a[4] = {U[k], U[3 * m.plane + k], U[6 * m.plane + k], U[9 * m.plane + k]};
-    if (ph.speed(0, a, bad) == tx) atomicMin(&sidx[0], (int)k);
-    if (ph.speed(1, a, bad) == ty) atomicMin(&sidx[1], (int)k);
+__global__ void __launch_bounds__(RED_T) adj_alpha_final_kernel(const double* __restrict__ pv,
+                                                                const int* __restrict__ pi, int nparts,
+                                                                double* smax, int* sidx) {
+  __shared__ double sv[2][RED_T / 64];
+  __shared__ int si[2][RED_T / 64];
+  double v[2] = {-1.0, -1.0};
+  int ix[2] = {INT_MAX, INT_MAX};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+    for (int d = 0; d < 2; ++d) argmax_merge(v[d], ix[d], pv[2 * b + d], pi[2 * b + d]);
+  for (int d = 0; d < 2; ++d) {
+    wave_argmax(v[d], ix[d]);
+    if ((threadIdx.x & 63) == 0) {
+      sv[d][threadIdx.x >> 6] = v[d];
+      si[d][threadIdx.x >> 6] = ix[d];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int d = threadIdx.x;
+    double vv = sv[d][0];
+    int ii = si[d][0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) argmax_merge(vv, ii, sv[d][q], si[d][q]);
+    smax[d] = vv < 0.0 ? 0.0 : vv;
+    sidx[d] = ii;
   }
 }
 
-__global__ void adj_alpha_route_kernel(AdjMesh m, const double* __restrict__ U, const double* __restrict__ partial,
-                                       int nblocks, const int* sidx, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+// d alpha_d / d U at the first maximal cell, times the summed alpha adjoints
+__global__ void __launch_bounds__(RED_T) adj_alpha_route_kernel(AdjMesh m, const double* __restrict__ U,
+                                                                const double* __restrict__ partial, int nblocks,
+                                                                const int* sidx, double* __restrict__ out) {
+  __shared__ double red[2][RED_T / 64];
   double ab[2] = {0.0, 0.0};
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     ab[0] += partial[2 * b];
     ab[1] += partial[2 * b + 1];
   }
   for (int d = 0; d < 2; ++d) {
+    ab[d] = wave_sum(ab[d]);
+    if ((threadIdx.x & 63) == 0) red[d][threadIdx.x >> 6] = ab[d];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int d = 0; d < 2; ++d) {
+    double tot = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) tot += red[d][q];
     if (sidx[d] < 0 || (size_t)sidx[d] >= m.plane) continue;   // no finite maximum
     const size_t k = (size_t)sidx[d];
     double a[4] = {U[k], U[3 * m.plane + k], U[6 * m.plane + k], U[9 * m.plane + k]};
     double gr[4];
     speed_grad(d, m.gamma, a, gr);
-    for (int c = 0; c < 4; ++c) out[(c * 3) * m.plane + k] += ab[d] * gr[c];
+    for (int c = 0; c < 4; ++c) out[(c * 3) * m.plane + k] += tot * gr[c];
   }
 }
 
@@ -656,11 +705,18 @@ __global__ void __launch_bounds__(ADJ_T) adj_seed_kernel(AdjMesh m, double x0, d
   if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void adj_sum_kernel(const double* __restrict__ partial, int n, double* out) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < n; ++b) s += partial[b];
-  *out = s;
+__global__ void __launch_bounds__(RED_T) adj_sum_kernel(const double* __restrict__ partial, int n, double* out) {
+  __shared__ double red[RED_T / 64];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) v += partial[b];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+    *out = t;
+  }
 }
 
 }  // namespace fam
@@ -672,30 +728,31 @@ struct FamAdjointScratch {
   size_t len = 0, cells = 0;
   int ncp = 0, seg = 0;
   double* ckpt = nullptr;     // ncp checkpoints
-  double* segbuf = nullptr;   // seg steps x 4 states
+  double* segbuf = nullptr;   // seg steps x 4 states (U0, U1, U2, Un)
   double* ucur = nullptr;
   double* lam = nullptr;
   double* lamN = nullptr;
   double* lam1 = nullptr;
   double* lam2 = nullptr;
   double* lam0 = nullptr;
-  double* abar = nullptr;
-  double* os = nullptr;
-  double* cb = nullptr;
-  double* partial = nullptr;
-  double* smax = nullptr;
-  int* sidx = nullptr;
+  double* abar = nullptr;     // coefficient adjoints [4][NCF][cells]
+  double* os = nullptr;       // OE record [32][cells]
+  double* cb = nullptr;       // face-centre adjoints [4][4][cells]
+  double* partial = nullptr;  // per-block alpha adjoints / functional sums
+  double* smax = nullptr;     // alpha_x, alpha_y
   double* Jd = nullptr;
+  double* apv = nullptr;      // argmax partials (values)
+  int* sidx = nullptr;        // first maximal cell in x, y
+  int* api = nullptr;         // argmax partials (indices)
 };
 
 void fam_adjoint_free(fam_ctx* c) {
   if (!c || !c->adj) return;
   FamAdjointScratch* s = c->adj;
-  double* bufs[] = {s->ckpt, s->segbuf, s->ucur, s->lam, s->lamN, s->lam1, s->lam2, s->lam0,
-                    s->abar, s->os, s->cb, s->partial, s->smax, s->Jd};
-  for (double* b : bufs)
+  void* bufs[] = {s->ckpt, s->segbuf, s->ucur, s->lam, s->lamN, s->lam1, s->lam2, s->lam0, s->abar,
+                  s->os, s->cb, s->partial, s->smax, s->Jd, s->apv, s->sidx, s->api};
+  for (void* b : bufs)
     if (b) (void)hipFree(b);
-  if (s->sidx) (void)hipFree(s->sidx);
   delete s;
   c->adj = nullptr;
 }
@@ -711,25 +768,23 @@ static fam_status adj_alloc(fam_ctx* c, int ncp, int seg) {
   s->cells = c->max_cells;
   s->ncp = ncp;
   s->seg = seg;
-  const size_t L = c->len * sizeof(double);
+  const size_t L = c->len * sizeof(double), D = sizeof(double);
   const size_t nb = ((c->cfg[0].nx + fam::ADJ_TX - 1) / fam::ADJ_TX) * ((c->cfg[0].ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
   struct A {
-    double** p;
+    void** p;
     size_t bytes;
-  } al[] = {{&s->ckpt, L * ncp}, {&s->segbuf, L * 4 * seg}, {&s->ucur, L}, {&s->lam, L}, {&s->lamN, L},
-            {&s->lam1, L}, {&s->lam2, L}, {&s->lam0, L},
-            {&s->abar, sizeof(double) * 4 * 21 * s->cells}, {&s->os, sizeof(double) * fam::OES * s->cells},
-            {&s->cb, sizeof(double) * 16 * s->cells}, {&s->partial, sizeof(double) * 2 * nb},
-            {&s->smax, sizeof(double) * 2}, {&s->Jd, sizeof(double)}};
+  } al[] = {{(void**)&s->ckpt, L * ncp}, {(void**)&s->segbuf, L * 4 * seg}, {(void**)&s->ucur, L},
+            {(void**)&s->lam, L}, {(void**)&s->lamN, L}, {(void**)&s->lam1, L}, {(void**)&s->lam2, L},
+            {(void**)&s->lam0, L}, {(void**)&s->abar, D * 4 * 21 * s->cells},
+            {(void**)&s->os, D * fam::OES * s->cells}, {(void**)&s->cb, D * 16 * s->cells},
+            {(void**)&s->partial, D * 2 * nb}, {(void**)&s->smax, D * 2}, {(void**)&s->Jd, D},
+            {(void**)&s->apv, D * 2 * fam::ALPHA_BLOCKS}, {(void**)&s->sidx, sizeof(int) * 2},
+            {(void**)&s->api, sizeof(int) * 2 * fam::ALPHA_BLOCKS}};
   for (auto& a : al)
     if (hipMalloc(a.p, a.bytes) != hipSuccess) {
       fam_adjoint_free(c);
       return FAM_ERR_NOMEM;
     }
-  if (hipMalloc(&s->sidx, sizeof(int) * 2) != hipSuccess) {
-    fam_adjoint_free(c);
-    return FAM_ERR_NOMEM;
-  }
   return FAM_OK;
 }
 
@@ -739,16 +794,15 @@ static void rT_apply(fam_ctx* c, const fam::AdjMesh& m, const double* Us, const 
   FamAdjointScratch* s = c->adj;
   const dim3 grid((m.nx + fam::ADJ_TX - 1) / fam::ADJ_TX, (m.ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
   const int nb = grid.x * grid.y;
-  // wave speeds of Us and their argmax
-  hipLaunchKernelGGL(fam::adj_alpha_init_kernel, dim3(1), dim3(64), 0, st, s->smax, s->sidx);
-  const int rb = (int)std::min<size_t>((m.plane + 255) / 256, 2048);
-  hipLaunchKernelGGL(fam::adj_alpha_max_kernel, dim3(rb), dim3(256), 0, st, m, Us, s->smax);
-  hipLaunchKernelGGL(fam::adj_alpha_arg_kernel, dim3(rb), dim3(256), 0, st, m, Us, s->smax, s->sidx);
+  // wave speeds of Us and their first argmax
+  hipLaunchKernelGGL(fam::adj_alpha_part_kernel, dim3(fam::ALPHA_BLOCKS), dim3(256), 0, st, m, Us, s->apv, s->api);
+  hipLaunchKernelGGL(fam::adj_alpha_final_kernel, dim3(1), dim3(fam::RED_T), 0, st, s->apv, s->api,
+                     fam::ALPHA_BLOCKS, s->smax, s->sidx);
   hipLaunchKernelGGL((fam::adj_coef_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Us, lam_out, b * dt, s->smax,
                      s->abar, s->partial);
   hipLaunchKernelGGL((fam::adj_gather_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, s->abar, lam_out, b, out,
                      accumulate);
-  hipLaunchKernelGGL(fam::adj_alpha_route_kernel, dim3(1), dim3(64), 0, st, m, Us, s->partial, nb, s->sidx, out);
+  hipLaunchKernelGGL(fam::adj_alpha_route_kernel, dim3(1), dim3(fam::RED_T), 0, st, m, Us, s->partial, nb, s->sidx, out);
 }
 
 template <int K>
@@ -795,7 +849,7 @@ static fam_status adjoint_k(fam_ctx* c, const double* U0, int nsteps, double dt,
   } else {
     hipLaunchKernelGGL(fam::adj_seed_kernel, grid, dim3(fam::ADJ_T), 0, st, m, f.x0, f.y0, s->ucur, s->lam,
                        s->partial);
-    hipLaunchKernelGGL(fam::adj_sum_kernel, dim3(1), dim3(64), 0, st, s->partial, nb, s->Jd);
+    hipLaunchKernelGGL(fam::adj_sum_kernel, dim3(1), dim3(fam::RED_T), 0, st, s->partial, nb, s->Jd);
   }
 
   // reverse sweep over the segments

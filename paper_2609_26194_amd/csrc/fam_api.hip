@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -216,6 +217,7 @@ extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx*
   c->max_cells = (size_t)f.nx * (f.dim == 2 ? f.ny : 1);
   c->len = c->max_cells * c->nc * c->nmom;
   c->H = f.dim == 2 ? choose_H(f.nx, f.ny) : 1;
+  c->H_oe = c->H;
   fam_status a = alloc_common(c);
   if (a == FAM_OK) a = init_steps(c);
   if (a == FAM_OK) a = build_inst_tables(c);
@@ -224,6 +226,37 @@ extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx*
     return a;
   }
   *out = c;
+  return FAM_OK;
+}
+
+// work list of a batch: (instance, i0, j0, H) strip tiles of height min(H, ny),
+// largest instances first (the persistent kernels take them round-robin)
+static fam_status build_work_list(fam_ctx* c, int Hmax) {
+  const int n = c->ninst;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (size_t)c->cfg[x].nx * c->cfg[x].ny > (size_t)c->cfg[y].nx * c->cfg[y].ny;
+  });
+  std::vector<int4> work;
+  c->inst_H.assign(n, Hmax);
+  for (int i : order) {
+    const fam_config& f = c->cfg[i];
+    const int H = std::min(Hmax, f.ny);
+    c->inst_H[i] = H;
+    for (int j0 = 0; j0 < f.ny; j0 += H)
+      for (int i0 = 0; i0 < f.nx; i0 += fam::STRIP) work.push_back(make_int4(i, i0, j0, H));
+  }
+  if (work.size() > c->work_cap) {
+    if (c->d_work) (void)hipFree(c->d_work);
+    c->d_work = nullptr;
+    c->work_cap = 0;
+    if (hipMalloc(&c->d_work, sizeof(int4) * work.size()) != hipSuccess) return FAM_ERR_NOMEM;
+    c->work_cap = work.size();
+  }
+  HIP_TRY(hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
+  c->nwork = (int)work.size();
+  c->batch_H = Hmax;
   return FAM_OK;
 }
 
@@ -262,27 +295,12 @@ extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_s
     fam_destroy(c);
     return a;
   }
-  // work list: (instance, i0, j0, H) tiles, largest instances first
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return (size_t)per[x].nx * per[x].ny > (size_t)per[y].nx * per[y].ny;
-  });
-  std::vector<int4> work;
-  c->inst_H.assign(n, 16);
-  for (int i : order) {
-    const int H = std::min(16, per[i].ny);
-    c->inst_H[i] = H;
-    for (int j0 = 0; j0 < per[i].ny; j0 += H)
-      for (int i0 = 0; i0 < per[i].nx; i0 += fam::STRIP) work.push_back(make_int4(i, i0, j0, H));
-  }
-  c->nwork = (int)work.size();
-  c->pblocks = std::min(c->nwork, 256 * 8);
-  if (hipMalloc(&c->d_work, sizeof(int4) * work.size()) != hipSuccess) { fam_destroy(c); return FAM_ERR_NOMEM; }
-  if (hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  fam_status w = build_work_list(c, 16);
+  if (w != FAM_OK) {
     fam_destroy(c);
-    return FAM_ERR_DEVICE;
+    return w;
   }
+  c->pblocks = std::min(c->nwork, 256 * 8);
   *out = c;
   return FAM_OK;
 }
@@ -353,7 +371,7 @@ void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const do
     if (c->dim == 1)
       fam::launch_oe1d(c->k, c->sys, A, in, c->stream);
     else
-      fam::launch_oe2d(c->k, c->sys, A, in, c->H, c->stream);
+      fam::launch_oe2d(c->k, c->sys, A, in, c->H_oe, c->stream);
   } else {
     fam::launch_oe2d_batched(c->k, c->sys, A, c->d_insts[parity][3], c->d_work, c->nwork, c->pblocks, c->stream);
   }
@@ -415,6 +433,100 @@ extern "C" fam_status fam_oe(fam_ctx* c, const double* Un, double* Uout, const d
   }
   enqueue_oe(c, 0, Un, Uout, dt_dev);
   return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: times the candidate launch shapes on the caller's state and keeps
+// the fastest.  Single 2D instance: the strip-tile height of the stage kernel
+// and of the OE kernel (the tile count against the 1024 wave slots of the chip
+// sets the tail of the last round of waves; shorter tiles add ring rows).
+// Batch: the tile height of the work list and the persistent grid size.
+// ---------------------------------------------------------------------------
+static fam_status time_launches(fam_ctx* c, int reps, const std::function<void()>& body, float* ms) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return FAM_ERR_DEVICE;
+  }
+  body();   // warm-up
+  fam_status r = FAM_OK;
+  if (hipEventRecord(e0, c->stream) != hipSuccess) r = FAM_ERR_DEVICE;
+  for (int i = 0; i < reps && r == FAM_OK; ++i) body();
+  if (r == FAM_OK && hipEventRecord(e1, c->stream) != hipSuccess) r = FAM_ERR_DEVICE;
+  if (r == FAM_OK && hipEventSynchronize(e1) != hipSuccess) r = FAM_ERR_DEVICE;
+  if (r == FAM_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) r = FAM_ERR_DEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r == FAM_OK && hipGetLastError() != hipSuccess) r = FAM_ERR_DEVICE;
+  return r;
+}
+
+extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* choice) {
+  if (!c || !U || reps < 1) return FAM_ERR_ARG;
+  if (c->dim != 2) return FAM_OK;   // 1D launch shapes are fixed
+  destroy_graphs(c);                // graphs hold the launch shapes they were captured with
+  fam_status r = reset_steps(c, 0.0, 0.0);
+  if (r != FAM_OK) return r;
+  enqueue_alpha_full(c, U, 0);
+  fam::launch_step_begin(c->st, c->ninst, 0, 0.0, 0.0, c->stream);
+  if (c->ninst == 1) {
+    const int ny = c->cfg[0].ny;
+    const int cand[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64};
+    float best_s = 1e30f, best_o = 1e30f;
+    int hs = c->H, ho = c->H_oe;
+    for (int H : cand) {
+      if (H > ny && H != cand[0]) continue;
+      c->H = c->H_oe = H;
+      float ms = 0.0f;
+      r = time_launches(c, reps, [&] { enqueue_stage(c, 1, 0, U, U, c->W1, nullptr); }, &ms);
+      if (r != FAM_OK) return r;
+      if (ms < best_s) { best_s = ms; hs = H; }
+      if (c->oe != FAM_OE_OFF) {
+        r = time_launches(c, reps, [&] { enqueue_oe(c, 0, U, c->W2, nullptr); }, &ms);
+        if (r != FAM_OK) return r;
+        if (ms < best_o) { best_o = ms; ho = H; }
+      }
+    }
+    c->H = hs;
+    c->H_oe = ho;
+    if (choice) {
+      choice[0] = hs;
+      choice[1] = ho;
+    }
+  } else {
+    const int candH[] = {8, 12, 16, 24, 32};
+    float best = 1e30f;
+    int bh = c->batch_H, bp = c->pblocks;
+    for (int H : candH) {
+      r = build_work_list(c, H);
+      if (r != FAM_OK) return r;
+      const int candP[] = {1024, 2048, 4096, c->nwork};
+      for (int P : candP) {
+        c->pblocks = std::max(1, std::min(P, c->nwork));
+        float ms = 0.0f;
+        r = time_launches(c, reps, [&] {
+          enqueue_stage(c, 1, 0, U, U, c->W1, nullptr);
+          if (c->oe != FAM_OE_OFF) enqueue_oe(c, 0, U, c->W2, nullptr);
+        }, &ms);
+        if (r != FAM_OK) return r;
+        if (ms < best) { best = ms; bh = H; bp = c->pblocks; }
+      }
+    }
+    r = build_work_list(c, bh);
+    if (r != FAM_OK) return r;
+    c->pblocks = bp;
+    if (choice) {
+      choice[0] = bh;
+      choice[1] = bp;
+    }
+  }
+  // the timing launches may have raised the device flag on the caller's state;
+  // the tuned kernels' outputs are discarded, so is the flag
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int z = 0;
+  HIP_TRY(hipMemcpy(c->flag, &z, sizeof(int), hipMemcpyHostToDevice));
+  return FAM_OK;
 }
 
 extern "C" fam_status fam_check(fam_ctx* c) {

@@ -29,12 +29,15 @@ struct fam_ctx {
   double* partial = nullptr;   // Type I partial sums
   double* dmax = nullptr;
   int t1_blocks = 256;
-  int H = 32;                  // rows per strip tile (single instance)
+  int H = 32;                  // rows per strip tile of the stage kernel (single instance)
+  int H_oe = 32;               // rows per strip tile of the OE kernel (single instance)
   // batched
   fam::Inst* d_insts[2][4] = {};    // [parity][stage 0..2, 3 = OE]
   fam::Inst* d_ainst[2] = {};       // [parity]: alpha_out = stage-0 input slot
   int4* d_work = nullptr;
   int nwork = 0;
+  size_t work_cap = 0;         // allocated work-list entries
+  int batch_H = 16;            // tile height of the batched work list
   int pblocks = 0;             // persistent grid size
   std::vector<int> inst_H;
   // graphs (keyed by U pointer, dt_fixed, t_final)

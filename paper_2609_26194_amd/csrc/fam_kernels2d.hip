@@ -109,30 +109,10 @@ __device__ __forceinline__ void gather(const Window& W, int c, int col, int sl, 
 // avg + theta2 (w - avg), w = p with its density scaled by theta1 toward the
 // average, theta1 and theta2 the largest values keeping density and pressure
 // >= eps = min(1e-13, rho_avg, p(avg)) at all 32 flux points of the cell.
+// Both scalings act on the deviation from the average, so they are applied to
+// the non-constant coefficients: rho by theta1 theta2, the other components by
+// theta2 (the same point values up to rounding).
 // ---------------------------------------------------------------------------
-template <int NC>
-struct Limiter {
-  bool active = false;
-  double th1 = 1.0, th2 = 1.0;
-  double avg[NC];
-  __device__ __forceinline__ void apply(double* v) const {
-    if (!active) return;
-    const double r = avg[0] + th1 * (v[0] - avg[0]);
-    v[0] = avg[0] + th2 * (r - avg[0]);
-#pragma unroll
-    for (int c = 1; c < NC; ++c) v[c] = avg[c] + th2 * (v[c] - avg[c]);
-  }
-  template <int Q>
-  __device__ __forceinline__ void apply_col(double (&v)[NC][Q], int q) const {
-    double t[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) t[c] = v[c][q];
-    apply(t);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) v[c][q] = t[c];
-  }
-};
-
 // smallest root in (0, 1] of a t^2 + b t + c (c > 0 and value <= 0 at t = 1), else 1
 __device__ __forceinline__ double smallest_root_unit(double a, double b, double c) {
   const double disc = fmax(b * b - 4.0 * a * c, 0.0);
@@ -146,79 +126,123 @@ __device__ __forceinline__ double smallest_root_unit(double a, double b, double 
   return r > 1.0 ? 1.0 : r;
 }
 
-// the 32 flux points in 8 groups of 4: right, left, top, bottom faces, then the
-// volume rows eta = node(qy), qy = 0..3
-template <int MD>
-__device__ __forceinline__ double point_of_group(const double (&E)[MD + 1][4], const double (&O)[MD + 1][3],
-                                                 int grp, int q) {
-  if (grp == 0) return eval_pt<MD>(E, O, 2, 1.0, qnode(q), qsign(q));
-  if (grp == 1) return eval_pt<MD>(E, O, 2, -1.0, qnode(q), qsign(q));
-  if (grp == 2) return eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
-  if (grp == 3) return eval_pt<MD>(E, O, qnode(q), qsign(q), 2, -1.0);
-  const int qy = grp - 4;
-  return eval_pt<MD>(E, O, qnode(q), qsign(q), qnode(qy), qsign(qy));
+
+__device__ __forceinline__ double bcast_lane(double x, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+  return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Called by all 64 lanes of the wave (uniform control flow).  Each lane first
+// runs a cheap sufficient test; the few cells that fail it (near
+// discontinuities) are then limited one at a time by the whole wave, lane l
+// evaluating flux point l mod 32 of that cell, so the exact test costs the wave
+// a few hundred instructions per such cell instead of a divergent 32-point loop.
 template <int K, int NCF, int MD, class P>
-__device__ __forceinline__ void pp_limiter(const P& phys, const double (&cf)[P::NC][NCF], Limiter<P::NC>& L,
-                                           bool& bad) {
+__device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NCF], bool& bad, int lane) {
   constexpr int NC = P::NC;
   if constexpr (NC != 4) {
     return;
   } else {
     const double g = phys.g;
+    double avg[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) L.avg[c] = cf[c][0];
-    const double inv = 1.0 / L.avg[0];
-    const double pa = phys.pressure(L.avg, inv);
-    if (!(L.avg[0] > 0.0) || !(pa > 0.0)) {
-      bad = true;
-      return;
-    }
-    const double eps = fmin(fmin(L.avg[0], pa), 1e-13);
-    // pass 1: minimum density over the 32 flux points
-    double rmin = 1e300;
-    {
-      double E[MD + 1][4], O[MD + 1][3];
-      contract_y<NCF, MD>(cf[0], E, O);
-#pragma unroll
-      for (int g = 0; g < 8; ++g)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rmin = fmin(rmin, point_of_group<MD>(E, O, g, q));
-    }
-    double th1 = 1.0;
-    if (rmin < eps) th1 = (L.avg[0] - eps) / (L.avg[0] - rmin);
-    // pass 2: pressure along avg -> density-limited point values, 4 points at a time
-    const double kk = 2.0 / (g - 1.0);
-    const double rho0 = L.avg[0], m0 = L.avg[1], n0 = L.avg[2], E0 = L.avg[3];
-    const double qc = 2.0 * rho0 * E0 - (m0 * m0 + n0 * n0) - kk * eps * rho0;
-    double th2 = 1.0;
-#pragma unroll
-    for (int grp = 0; grp < 8; ++grp) {
-      double v[NC][4];
+    for (int c = 0; c < NC; ++c) avg[c] = cf[c][0];
+    const double inv = 1.0 / avg[0];
+    const double pa = phys.pressure(avg, inv);
+    const bool adm = (avg[0] > 0.0) && (pa > 0.0);
+    if (!adm) bad = true;
+    const double eps = fmin(fmin(avg[0], pa), 1e-13);
+    // cheap sufficient test: every basis function is bounded by its value at the
+    // cell corner (|L_m| <= L_m(1/2) on [-1/2, 1/2]), which bounds each
+    // component's deviation from its average; if density and the pressure lower
+    // bound built from those deviations stay above eps (with a rounding margin),
+    // no point can violate and the limiter is the identity.
+    bool need = false;
+    if (adm && lane >= 1 && lane <= LANES - 2) {
+      double dev[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        double E[MD + 1][4], O[MD + 1][3];
-        contract_y<NCF, MD>(cf[c], E, O);
+        dev[c] = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[c][q] = point_of_group<MD>(E, O, grp, q);
+        for (int l = 1; l < NCF; ++l) dev[c] = fma(fabs(cf[c][l]), leg(AX[l], 0.5) * leg(AY[l], 0.5), dev[c]);
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double w0 = rho0 + th1 * (v[0][q] - rho0);
-        const double w[4] = {w0, v[1][q], v[2][q], v[3][q]};
-        const double pw = phys.pressure(w, 1.0 / w0);
-        if (pw < eps) {
-          const double rd = w0 - rho0, md = w[1] - m0, nd = w[2] - n0, Ed = w[3] - E0;
-          const double qa = 2.0 * rd * Ed - (md * md + nd * nd);
-          const double qb = 2.0 * (rho0 * Ed + rd * E0) - 2.0 * (m0 * md + n0 * nd) - kk * eps * rd;
-          th2 = fmin(th2, smallest_root_unit(qa, qb, qc));
-        }
+      const double rlo = avg[0] - dev[0];
+      const double mm = fabs(avg[1]) + dev[1], nn = fabs(avg[2]) + dev[2];
+      const double margin = 1e-12 * (avg[0] + dev[0] + fabs(avg[3]) + dev[3]);
+      need = true;
+      if (rlo > eps + margin) {
+        const double plo = (g - 1.0) * (avg[3] - dev[3] - 0.5 * (mm * mm + nn * nn) / rlo);
+        if (plo > eps + margin) need = false;
       }
     }
-    L.th1 = th1;
-    L.th2 = th2;
-    L.active = (th1 < 1.0) || (th2 < 1.0);
+    unsigned long long todo = __ballot(need);
+    if (todo == 0) return;
+    // basis values at this lane's flux point: right face (1/2, eta_g), left face
+    // (-1/2, eta_g), top face (xi_g, 1/2), bottom face (xi_g, -1/2), volume
+    // points (xi_a, eta_b) at 16 + 4 b + a
+    const int pt = lane & 31;
+    const double nd[4] = {-GS1, -GS0, GS0, GS1};
+    double px, py;
+    if (pt < 4) { px = 0.5; py = nd[pt]; }
+    else if (pt < 8) { px = -0.5; py = nd[pt - 4]; }
+    else if (pt < 12) { px = nd[pt - 8]; py = 0.5; }
+    else if (pt < 16) { px = nd[pt - 12]; py = -0.5; }
+    else { px = nd[(pt - 16) & 3]; py = nd[(pt - 16) >> 2]; }
+    double phi[NCF];
+#pragma unroll
+    for (int l = 0; l < NCF; ++l) phi[l] = leg(AX[l], px) * leg(AY[l], py);
+    const double kk = 2.0 / (g - 1.0);
+    double th1 = 1.0, th2 = 1.0;
+    while (todo) {
+      const int src = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      double v[NC], a[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        v[c] = 0.0;
+#pragma unroll
+        for (int l = 0; l < NCF; ++l) v[c] = fma(bcast_lane(cf[c][l], src), phi[l], v[c]);
+        a[c] = bcast_lane(avg[c], src);
+      }
+      const double e = bcast_lane(eps, src);
+      // density: theta1 from the minimum over the 32 points
+      const double rmin = wave_min(v[0]);
+      const double t1 = rmin < e ? (a[0] - e) / (a[0] - rmin) : 1.0;
+      // pressure along avg -> density-limited point value
+      const double rho0 = a[0], m0 = a[1], n0 = a[2], E0 = a[3];
+      const double w0 = rho0 + t1 * (v[0] - rho0);
+      const double w[4] = {w0, v[1], v[2], v[3]};
+      const double pw = phys.pressure(w, 1.0 / w0);
+      double t2 = 1.0;
+      if (pw < e) {
+        const double qc = 2.0 * rho0 * E0 - (m0 * m0 + n0 * n0) - kk * e * rho0;
+        const double rd = w0 - rho0, md = w[1] - m0, nd_ = w[2] - n0, Ed = w[3] - E0;
+        const double qa = 2.0 * rd * Ed - (md * md + nd_ * nd_);
+        const double qb = 2.0 * (rho0 * Ed + rd * E0) - 2.0 * (m0 * md + n0 * nd_) - kk * e * rd;
+        t2 = smallest_root_unit(qa, qb, qc);
+      }
+      t2 = wave_min(t2);
+      if (lane == src) {
+        th1 = t1;
+        th2 = t2;
+      }
+    }
+    if (th1 < 1.0 || th2 < 1.0) {
+      const double t0 = th1 * th2;
+#pragma unroll
+      for (int l = 1; l < NCF; ++l) cf[0][l] *= t0;
+#pragma unroll
+      for (int c = 1; c < NC; ++c)
+#pragma unroll
+        for (int l = 1; l < NCF; ++l) cf[c][l] *= th2;
+    }
   }
 }
 
@@ -292,8 +316,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
     }
 
     // optional positivity limiter on this cell's reconstruction
-    Limiter<NC> lim;
-    if constexpr (PP) pp_limiter<K, NCF, MD>(phys, cf, lim, bad);
+    if constexpr (PP) pp_limiter<K, NCF, MD>(phys, cf, bad, lane);
 
     // bottom trace -> y-face flux below the current row: (i, r-1/2)
     double Gb[NC], Gt[NC];
@@ -307,10 +330,6 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
         contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
         for (int q = 0; q < 4; ++q) bt[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, -1.0);
-      }
-      if constexpr (PP) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) lim.apply_col(bt, q);
       }
       if (!ring_lo) {
 #pragma unroll
@@ -358,10 +377,6 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 #pragma unroll
       for (int q = 0; q < 4; ++q) prevTop[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
     }
-    if constexpr (PP) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) lim.apply_col(prevTop, q);
-    }
 
     if (!ring_lo) {
       // x-face left of this lane: (i-1/2, r); left state = right trace of lane-1
@@ -378,13 +393,6 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
           for (int q = 0; q < 4; ++q) {
             rt[c][q] = eval_pt<MD>(E, O, 2, 1.0, qnode(q), qsign(q));
             lt[c][q] = eval_pt<MD>(E, O, 2, -1.0, qnode(q), qsign(q));
-          }
-        }
-        if constexpr (PP) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            lim.apply_col(rt, q);
-            lim.apply_col(lt, q);
           }
         }
 #pragma unroll
@@ -424,10 +432,6 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
           contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) vals[qq][c] = eval_pt<MD>(E, O, qnode(qq), qsign(qq), qnode(qy), qsign(qy));
-        }
-        if constexpr (PP) {
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) lim.apply(vals[qq]);
         }
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {

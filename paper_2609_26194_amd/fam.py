@@ -109,6 +109,7 @@ def load_library():
         "fam_oe": (I, [VP, VP, VP, VP]),
         "fam_check": (I, [VP]),
         "fam_adjoint": (I, [VP, VP, I, D, I, VP, VP, P]),
+        "fam_autotune": (I, [VP, VP, I, ctypes.POINTER(I)]),
         "fam_destroy": (None, [VP]),
         "fam_status_str": (ctypes.c_char_p, [I]),
     }
@@ -194,6 +195,12 @@ def fam_adjoint(h, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0):
     _check(load_library().fam_adjoint(h, _ptr(U0), int(nsteps), float(dt), int(checkpoint_every),
                                       _ptr(dJdUT), _ptr(dJdU0), ctypes.byref(J)), "fam_adjoint")
     return J.value
+
+
+def fam_autotune(h, U, reps=5):
+    choice = (ctypes.c_int * 2)()
+    _check(load_library().fam_autotune(h, _ptr(U), int(reps), choice), "fam_autotune")
+    return int(choice[0]), int(choice[1])
 
 
 def fam_state_len(h):
@@ -292,6 +299,11 @@ class Fam:
 
     def check(self):
         return self._call(fam_check)
+
+    def autotune(self, U, reps=5):
+        """Pick the fastest launch shapes for this context on state U (read only)."""
+        self._state(U)
+        return self._call(fam_autotune, U, reps)
 
     def adjoint(self, U0, nsteps, dt, checkpoint_every, dJdUT=None):
         self._state(U0)

@@ -195,6 +195,12 @@ def test_pp_limiter_makes_flux_points_admissible():
     lim = pp_apply(vals, avg, th1, th2)
     assert float(lim[0].min()) > 0 and float(ph.pressure(lim).min()) > 0
     assert float(th2.min()) < 1 and float(th2.max()) == 1.0
+    # tightness: where the pressure scaling is active, the smallest limited pressure
+    # over the 32 points sits at the floor eps <= 1e-13 (up to rounding), so the
+    # scaling is the largest admissible one, not merely an admissible one
+    active = th2 < 1.0
+    pmin = ph.pressure(lim).min(dim=0).values
+    assert float(pmin[active].max()) < 1e-10
     # the limited reconstruction keeps the cell average (volume-point quadrature)
     _, w = gauss4()
     W = torch.tensor([w[q % 4] * w[q // 4] for q in range(16)], dtype=torch.float64)
