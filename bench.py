@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6          # 256 CUs x 2.4 GHz x 128 FP64 flops / clock
 COPY_BYTES = 1 << 30             # calibration copy for the HBM counters
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "stage2d_k5_2048_counters.json")
-STAGE_SOURCES = ["fam_kernels2d.hip", "fam_device.h", "fam_eval.h", "fam_kernels.h"]
+STAGE_SOURCES = ["fam_kernels2d.hip", "fam_device.h", "fam_eval.h", "fam_kernels.h", "fam_strip.h"]
 
 
 def parse():

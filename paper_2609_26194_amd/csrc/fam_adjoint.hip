@@ -52,12 +52,18 @@ struct AdjMesh {
   double dx, dy, gamma;
 };
 
+__device__ __forceinline__ int wrap1(int i, int n) {
+  if (i < 0) i += n;
+  else if (i >= n) i -= n;
+  if ((unsigned)i >= (unsigned)n) {   // offsets beyond one period (tiny meshes)
+    i %= n;
+    if (i < 0) i += n;
+  }
+  return i;
+}
+
 __device__ __forceinline__ size_t wrap_idx(const AdjMesh& m, int i, int j) {
-  i %= m.nx;
-  if (i < 0) i += m.nx;
-  j %= m.ny;
-  if (j < 0) j += m.ny;
-  return (size_t)j * m.nx + i;
+  return (size_t)wrap1(j, m.ny) * m.nx + wrap1(i, m.nx);
 }
 
 // stencil of component c around cell (i, j) (periodic)
@@ -80,7 +86,7 @@ __device__ __forceinline__ void gstencil(const double* __restrict__ U, const Adj
 
 // out = J_d(u)^T w for the 2D Euler flux in direction d
 __device__ __forceinline__ void euler_jt(int d, double g, const double* u, const double* w, double* out) {
-  const double inv = 1.0 / u[0];
+  const double inv = rcp(u[0]);
   const double vx = u[1] * inv, vy = u[2] * inv;
   const double q2 = vx * vx + vy * vy;
   const double g1 = g - 1.0;
@@ -98,6 +104,26 @@ __device__ __forceinline__ void euler_jt(int d, double g, const double* u, const
     out[2] = w[0] + vx * w[1] + (3.0 - g) * vy * w[2] + (H - g1 * vy * vy) * w[3];
     out[3] = g1 * w[2] + g * vy * w[3];
   }
+}
+
+// out = J_1(u)^T w1 + J_2(u)^T w2 (volume points: both directions share the primitives)
+__device__ __forceinline__ void euler_jt2(double g, const double* u, const double* w1, const double* w2,
+                                          double* out) {
+  const double inv = rcp(u[0]);
+  const double vx = u[1] * inv, vy = u[2] * inv;
+  const double q2 = vx * vx + vy * vy;
+  const double g1 = g - 1.0;
+  const double p = g1 * (u[3] - 0.5 * u[0] * q2);
+  const double H = (u[3] + p) * inv;
+  const double k = 0.5 * g1 * q2;
+  const double vxy = vx * vy;
+  out[0] = (-vx * vx + k) * w1[1] - vxy * (w1[2] + w2[1]) + vx * (k - H) * w1[3] + (-vy * vy + k) * w2[2] +
+           vy * (k - H) * w2[3];
+  out[1] = w1[0] + (3.0 - g) * vx * w1[1] + vy * (w1[2] + w2[1]) + (H - g1 * vx * vx) * w1[3] -
+           g1 * vx * w2[2] - g1 * vxy * w2[3];
+  out[2] = -g1 * vy * w1[1] + vx * (w1[2] + w2[1]) - g1 * vxy * w1[3] + w2[0] + (3.0 - g) * vy * w2[2] +
+           (H - g1 * vy * vy) * w2[3];
+  out[3] = g1 * (w1[1] + w2[2]) + g * (vx * w1[3] + vy * w2[3]);
 }
 
 // gradient of |u_d| + sqrt(g p / rho) with respect to (rho, m, n, E)
@@ -119,21 +145,6 @@ __device__ __forceinline__ void speed_grad(int d, double g, const double* u, dou
 
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// phi_l at (sx * node(gx), sy * node(gy))
-template <int L>
-__device__ __forceinline__ constexpr double phi_at(int gx, double sx, int gy, double sy) {
-  double px = legn(AX[L], gx), py = legn(AY[L], gy);
-  if (AX[L] % 2) px *= sx;
-  if (AY[L] % 2) py *= sy;
-  return px * py;
-}
-
-template <int NCF, int... L>
-__device__ __forceinline__ void add_phi(double* abar, double ub, int gx, double sx, int gy, double sy,
-                                        std::integer_sequence<int, L...>) {
-  ((abar[L] = fma(ub, phi_at<L>(gx, sx, gy, sy), abar[L])), ...);
-}
-
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -147,13 +158,105 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ---------------------------------------------------------------------------
 // (1) coefficient adjoints of R^T(U) mu, mu = scale * lam_out
+//
+// The 32 flux points form 8 groups of 4 sign-symmetric points (sx X, sy Y):
+// groups 0, 1: x-faces (X = 1/2, Y = GS0 / GS1; sx = +1 right face, -1 left);
+// groups 2, 3: y-faces (X = GS0 / GS1, Y = 1/2; sy = +1 top face, -1 bottom);
+// groups 4..7: volume points (X, Y) in {GS0, GS1}^2.
+// phi_l(sx X, sy Y) = phi_l(X, Y) sx^(ax_l odd) sy^(ay_l odd), so the point values
+// of a group come from four parity sums of the coefficients, and the transposed
+// evaluation from four signed sums of the point adjoints.
 // ---------------------------------------------------------------------------
+// face adjoint weights of the face between cells L (left / below) and R:
+// d J / d Fbar and d J / d Ftil (x-face), d J / d Gbar and d J / d Gtil (y-face)
+__device__ __forceinline__ void face_adj(bool xface, const double (&muL)[3], const double (&muR)[3], double inv,
+                                         double& B, double& T) {
+  if (xface) {
+    B = (-muL[0] - 0.5 * muL[1] + muR[0] - 0.5 * muR[1]) * inv;
+    T = (-muL[2] + muR[2]) * inv;
+  } else {
+    B = (-muL[0] - 0.5 * muL[2] + muR[0] - 0.5 * muR[2]) * inv;
+    T = (-muL[1] + muR[1]) * inv;
+  }
+}
+
+__device__ __forceinline__ void load_mu(const double* __restrict__ lam, const AdjMesh& m, size_t id, double scale,
+                                        double (&mu)[4][3]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) mu[c][r] = scale * lam[(c * 3 + r) * m.plane + id];
+}
+
+// G: group index; for face groups B/T hold [side][c] for the two faces of the group
+// (side 0: sign +1 face, side 1: sign -1 face)
+template <int K, int G>
+__device__ __forceinline__ void coef_group(double g, const double (&cf)[4][ncoef2d(K)], double (&ab)[4][ncoef2d(K)],
+                                           const double (&mu)[4][3], double idx_, double idy,
+                                           const double (&B)[2][4], const double (&T)[2][4], double al,
+                                           double& pa) {
+  constexpr int NCF = ncoef2d(K);
+  using Seq = std::make_integer_sequence<int, NCF>;
+  constexpr int NXI = G < 2 ? 2 : G < 4 ? (G - 2) : ((G - 4) & 1);
+  constexpr int NYI = G < 2 ? G : G < 4 ? 2 : ((G - 4) >> 1);
+  constexpr bool XF = G < 2, YF = (G >= 2 && G < 4);
+  double u[4][4];   // [point][component]
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double P[4];
+    parity_sums<NXI, NYI>(cf[c], P, Seq{});
+#pragma unroll
+    for (int s = 0; s < 4; ++s) u[s][c] = P[0] + grp_sx(s) * P[1] + grp_sy(s) * P[2] + grp_sx(s) * grp_sy(s) * P[3];
+  }
+  double ub[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if constexpr (XF || YF) {
+      // face point: side by the sign across the face, Gauss node by the sign along it
+      const int side = XF ? (grp_sx(s) > 0 ? 0 : 1) : (grp_sy(s) > 0 ? 0 : 1);
+      const double eta = XF ? grp_sy(s) * (NYI == 0 ? GS0 : GS1) : grp_sx(s) * (NXI == 0 ? GS0 : GS1);
+      const double w = XF ? (NYI == 0 ? GW0 : GW1) : (NXI == 0 ? GW0 : GW1);
+      const double sgn = side == 0 ? 1.0 : -1.0;
+      double Fh[4], half[4], jt[4];
+      double dot = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Fh[c] = w * (B[side][c] + eta * T[side][c]);
+        half[c] = 0.5 * Fh[c];
+        dot = fma(Fh[c], u[s][c], dot);
+      }
+      euler_jt(XF ? 0 : 1, g, u[s], half, jt);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ub[s][c] = jt[c] + sgn * 0.5 * al * Fh[c];
+      pa += sgn * 0.5 * dot;
+    } else {
+      constexpr double w = (NXI == 0 ? GW0 : GW1) * (NYI == 0 ? GW0 : GW1);
+      double w1[4], w2[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        w1[c] = w * mu[c][1] * idx_;
+        w2[c] = w * mu[c][2] * idy;
+      }
+      euler_jt2(g, u[s], w1, w2, ub[s]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double Q[4];
+    Q[0] = ub[0][c] + ub[1][c] + ub[2][c] + ub[3][c];
+    Q[1] = ub[0][c] + ub[1][c] - ub[2][c] - ub[3][c];
+    Q[2] = ub[0][c] - ub[1][c] + ub[2][c] - ub[3][c];
+    Q[3] = ub[0][c] - ub[1][c] - ub[2][c] + ub[3][c];
+    parity_scatter<NXI, NYI>(ab[c], Q, Seq{});
+  }
+}
+
 template <int K>
 __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double* __restrict__ U,
                                                          const double* __restrict__ lam, double scale,
                                                          const double* __restrict__ alpha,
                                                          double* __restrict__ abar, double* __restrict__ partial) {
-  constexpr int NC = 4, NCF = ncoef2d(K), MD = maxdeg(K);
+  constexpr int NC = 4, NCF = ncoef2d(K);
   __shared__ double red[ADJ_T / 64];
   const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
   const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
@@ -173,112 +276,47 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
 #pragma unroll
       for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
     }
-    // mu of this cell and of its four neighbours: [self, left, right, bottom, top][c][m]
-    double mu[5][NC][3];
-    const size_t ids[5] = {wrap_idx(m, i, j), wrap_idx(m, i - 1, j), wrap_idx(m, i + 1, j),
-                           wrap_idx(m, i, j - 1), wrap_idx(m, i, j + 1)};
-#pragma unroll
-    for (int n = 0; n < 5; ++n)
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int r = 0; r < 3; ++r) mu[n][c][r] = scale * lam[(c * 3 + r) * m.plane + ids[n]];
+    const size_t id = wrap_idx(m, i, j);
+    double mu[NC][3];
+    load_mu(lam, m, id, scale, mu);
     double ab[NC][NCF];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int l = 0; l < NCF; ++l) ab[c][l] = 0.0;
-    using Seq = std::make_integer_sequence<int, NCF>;
-
-    // volume: V1 = sum w f1(u), V2 = sum w f2(u); R1 += V1/dx, R2 += V2/dy
+    double B[2][4], T[2][4];
+    // x-faces: side 0 = right face (this cell on the left), side 1 = left face
+    {
+      double nb[NC][3];
+      load_mu(lam, m, wrap_idx(m, i + 1, j), scale, nb);
 #pragma unroll
-    for (int qy = 0; qy < 4; ++qy)
+      for (int c = 0; c < NC; ++c) face_adj(true, mu[c], nb[c], idx_, B[0][c], T[0][c]);
+      load_mu(lam, m, wrap_idx(m, i - 1, j), scale, nb);
 #pragma unroll
-      for (int qx = 0; qx < 4; ++qx) {
-        double u[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          double E[MD + 1][4], O[MD + 1][3];
-          contract_y<NCF, MD>(cf[c], E, O);
-          u[c] = eval_pt<MD>(E, O, qnode(qx), qsign(qx), qnode(qy), qsign(qy));
-        }
-        const double w = qw(qx) * qw(qy);
-        double w1[NC], w2[NC], o1[NC], o2[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          w1[c] = w * mu[0][c][1] * idx_;
-          w2[c] = w * mu[0][c][2] * idy;
-        }
-        euler_jt(0, g, u, w1, o1);
-        euler_jt(1, g, u, w2, o2);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          add_phi<NCF>(ab[c], o1[c] + o2[c], qnode(qx), qsign(qx), qnode(qy), qsign(qy), Seq{});
-      }
-
-    // faces: side 0 right (cell is left state), 1 left (cell is right state),
-    //        2 top (cell is lower state), 3 bottom (cell is upper state)
-#pragma unroll
-    for (int side = 0; side < 4; ++side) {
-      const bool xf = side < 2;
-      const bool own_left = (side == 0 || side == 2);
-      const int nb = side == 0 ? 2 : side == 1 ? 1 : side == 2 ? 4 : 3;   // neighbour slot in mu[]
-      double Badj[NC], Tadj[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        // mu of the lower/left cell (L) and upper/right cell (R) of this face
-        const double* muL = own_left ? mu[0][c] : mu[nb][c];
-        const double* muR = own_left ? mu[nb][c] : mu[0][c];
-        if (xf) {
-          Badj[c] = -muL[0] * idx_ - 0.5 * muL[1] * idx_ + muR[0] * idx_ - 0.5 * muR[1] * idx_;
-          Tadj[c] = -muL[2] * idx_ + muR[2] * idx_;
-        } else {
-          Badj[c] = -muL[0] * idy - 0.5 * muL[2] * idy + muR[0] * idy - 0.5 * muR[2] * idy;
-          Tadj[c] = -muL[1] * idy + muR[1] * idy;
-        }
-      }
-      const double al = xf ? ax : ay;
-      const double sgn_side = own_left ? 1.0 : -1.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double u[NC];
-        const int gxn = xf ? 2 : qnode(q), gyn = xf ? qnode(q) : 2;
-        const double sxv = xf ? (side == 0 ? 1.0 : -1.0) : qsign(q);
-        const double syv = xf ? qsign(q) : (side == 2 ? 1.0 : -1.0);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          double E[MD + 1][4], O[MD + 1][3];
-          contract_y<NCF, MD>(cf[c], E, O);
-          u[c] = eval_pt<MD>(E, O, gxn, sxv, gyn, syv);
-        }
-        double Fh[NC], jt[NC];
-        double dotFu = 0.0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          Fh[c] = qw(q) * Badj[c] + qw(q) * qx(q) * Tadj[c];
-          dotFu = fma(Fh[c], u[c], dotFu);
-        }
-        double half[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) half[c] = 0.5 * Fh[c];
-        euler_jt(xf ? 0 : 1, g, u, half, jt);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double ub = jt[c] + sgn_side * 0.5 * al * Fh[c];
-          add_phi<NCF>(ab[c], ub, gxn, sxv, gyn, syv, Seq{});
-        }
-        if (xf)
-          pax += sgn_side * 0.5 * dotFu;
-        else
-          pay += sgn_side * 0.5 * dotFu;
-      }
+      for (int c = 0; c < NC; ++c) face_adj(true, nb[c], mu[c], idx_, B[1][c], T[1][c]);
     }
-    const size_t id = ids[0];
-    const size_t cells = m.plane;
+    coef_group<K, 0>(g, cf, ab, mu, idx_, idy, B, T, ax, pax);
+    coef_group<K, 1>(g, cf, ab, mu, idx_, idy, B, T, ax, pax);
+    // y-faces: side 0 = top face (this cell below), side 1 = bottom face
+    {
+      double nb[NC][3];
+      load_mu(lam, m, wrap_idx(m, i, j + 1), scale, nb);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) face_adj(false, mu[c], nb[c], idy, B[0][c], T[0][c]);
+      load_mu(lam, m, wrap_idx(m, i, j - 1), scale, nb);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) face_adj(false, nb[c], mu[c], idy, B[1][c], T[1][c]);
+    }
+    coef_group<K, 2>(g, cf, ab, mu, idx_, idy, B, T, ay, pay);
+    coef_group<K, 3>(g, cf, ab, mu, idx_, idy, B, T, ay, pay);
+    coef_group<K, 4>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    coef_group<K, 5>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    coef_group<K, 6>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    coef_group<K, 7>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int l = 0; l < NCF; ++l) abar[(size_t)(c * NCF + l) * cells + id] = ab[c][l];
+      for (int l = 0; l < NCF; ++l) abar[(size_t)(c * NCF + l) * m.plane + id] = ab[c][l];
   }
   const double sx = block_sum(pax, red);
   const double sy = block_sum(pay, red);
@@ -297,56 +335,84 @@ __device__ __forceinline__ double rt_apply(const double* a) {
   return rt_dot<K, IN>(a, std::make_integer_sequence<int, ncoef2d(K)>{});
 }
 
-template <int K, int DX, int DY>
-__device__ __forceinline__ void gather_one(const AdjMesh& m, int i, int j, const double* __restrict__ abar,
-                                           double (&acc)[4][3]) {
-  constexpr int NCF = ncoef2d(K);
-  constexpr int L9 = (1 - DX) + 3 * (1 - DY);   // position of q in the patch of n = q + (DX, DY)
-  const size_t id = wrap_idx(m, i + DX, j + DY);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double a[NCF];
-#pragma unroll
-    for (int l = 0; l < NCF; ++l) a[l] = abar[(size_t)(c * NCF + l) * m.plane + id];
-    acc[c][0] += rt_apply<K, L9>(a);
-    acc[c][1] += rt_apply<K, 9 + L9>(a);
-    acc[c][2] += rt_apply<K, 18 + L9>(a);
-  }
-}
+// LDS tile of one component's coefficient adjoints over the block's cells and a
+// one-cell ring (periodic wrap)
+constexpr int GT = ADJ_TX + 2;                 // 18 x 18 tile
+constexpr int GTC = GT * GT;
 
 template <int K>
 __global__ void __launch_bounds__(ADJ_T) adj_gather_kernel(AdjMesh m, const double* __restrict__ abar,
                                                            const double* __restrict__ lam_out, double b,
-                                                           double* __restrict__ out, int accumulate) {
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
-  if (i >= m.nx || j >= m.ny) return;
-  double acc[4][3] = {};
-  gather_one<K, -1, -1>(m, i, j, abar, acc);
-  gather_one<K, 0, -1>(m, i, j, abar, acc);
-  gather_one<K, 1, -1>(m, i, j, abar, acc);
-  gather_one<K, -1, 0>(m, i, j, abar, acc);
-  gather_one<K, 0, 0>(m, i, j, abar, acc);
-  gather_one<K, 1, 0>(m, i, j, abar, acc);
-  gather_one<K, -1, 1>(m, i, j, abar, acc);
-  gather_one<K, 0, 1>(m, i, j, abar, acc);
-  gather_one<K, 1, 1>(m, i, j, abar, acc);
+                                                           double* __restrict__ out, int accumulate,
+                                                           double* __restrict__ out2, double b2, int acc2) {
+  constexpr int NCF = ncoef2d(K);
+  __shared__ double sh[NCF][GTC];
+  const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
+  const int i0 = blockIdx.x * ADJ_TX, j0 = blockIdx.y * ADJ_TY;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool inside = i < m.nx && j < m.ny;
+  double acc[4][3];
+  // tile positions this thread loads (GTC = 324 > ADJ_T: at most two)
+  constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;
+  size_t src[NLP];
+#pragma unroll
+  for (int t = 0; t < NLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+    const int py = p / GT, px = p - py * GT;
+    src[t] = p < GTC ? wrap_idx(m, i0 - 1 + px, j0 - 1 + py) : 0;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NLP; ++t) {
+      const int p = threadIdx.x + t * ADJ_T;
+      if (p < GTC) {
+#pragma unroll
+        for (int l = 0; l < NCF; ++l) sh[l][p] = abar[(size_t)(c * NCF + l) * m.plane + src[t]];
+      }
+    }
+    __syncthreads();
+    acc[c][0] = acc[c][1] = acc[c][2] = 0.0;
+    if (inside) {
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int pos = (ty + 1 + dy) * GT + (tx + 1 + dx);
+          double a[NCF];
+#pragma unroll
+          for (int l = 0; l < NCF; ++l) a[l] = sh[l][pos];
+          // position of this cell in the patch of the neighbour n = q + (dx, dy)
+          const int L9 = (1 - dx) + 3 * (1 - dy);
+          switch (L9) {
+#define FAM_RT3(P)                              \
+  case P:                                       \
+    acc[c][0] += rt_apply<K, P>(a);             \
+    acc[c][1] += rt_apply<K, 9 + P>(a);         \
+    acc[c][2] += rt_apply<K, 18 + P>(a);        \
+    break;
+            FAM_RT3(0) FAM_RT3(1) FAM_RT3(2) FAM_RT3(3) FAM_RT3(4) FAM_RT3(5) FAM_RT3(6) FAM_RT3(7) FAM_RT3(8)
+#undef FAM_RT3
+          }
+        }
+    }
+  }
+  if (!inside) return;
   const size_t id = (size_t)j * m.nx + i;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const size_t k = (c * 3 + r) * m.plane + id;
-      const double v = b * lam_out[k] + acc[c][r];
+      const double lo = lam_out[k];
+      const double v = b * lo + acc[c][r];
       out[k] = accumulate ? out[k] + v : v;
+      // second output: out2 (+)= b2 lam_out (the Shu-Osher U0 terms)
+      if (out2) out2[k] = acc2 ? out2[k] + b2 * lo : b2 * lo;
     }
 }
 
-__global__ void adj_axpy_kernel(size_t n, double a, const double* __restrict__ x, double* __restrict__ y,
-                                int accumulate) {
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-    y[k] = accumulate ? y[k] + a * x[k] : a * x[k];
-}
 
 // ---------------------------------------------------------------------------
 // (3) alpha: argmax of the spectral radii at the averages and its route
@@ -457,65 +523,82 @@ __global__ void __launch_bounds__(RED_T) adj_alpha_route_kernel(AdjMesh m, const
 // ---------------------------------------------------------------------------
 // OE adjoint (Type II)
 // ---------------------------------------------------------------------------
-// per-cell record: [0..3] jump at the left face, [4..7] jump at the bottom face,
-// [8..11] dJ/dJx, [12..15] dJ/dJy, [16..19] dJ/dD, [20..23] sign(u_p* - S),
-// [24..27] p* (patch index), 28 dJ/dbeta_x, 29 dJ/dbeta_y, 30, 31 argmax patch index
-constexpr int OES = 32;
+// pre-pass record per cell (CS planes): [4c + f] face-centre value f (r, l, t, b)
+// of component c, 16, 17: spectral radii in x and y at the cell average.
+constexpr int CS = 18;
+// per-cell record (OES planes): [0..3] jump at the left face, [4..7] jump at the
+// bottom face, [8..11] dJ/dJx, [12..15] dJ/dJy (read by the face pass);
+// [16..19] dJ/dD * sign(u_p* - S), 20 packed patch indices (p* of the four
+// components, argmax beta_x, argmax beta_y; 4 bits each), 21, 22 dJ/dbeta_x, y
+// (read by the gather pass).
+constexpr int OES = 23;
 
 template <int K>
-__device__ __forceinline__ void centres_at(const double* __restrict__ U, const AdjMesh& m, int c, int i, int j,
-                                           double (&out)[4]) {
-  double u0[9], u1[9], u2[9];
-  gstencil<K>(U, m, c, i, j, u0, u1, u2);
-  double u[27];
-#pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    u[l] = u0[l];
-    u[9 + l] = u1[l];
-    u[18 + l] = u2[l];
-  }
+__global__ void __launch_bounds__(ADJ_T) oe_adj_pre_kernel(AdjMesh m, const double* __restrict__ Un,
+                                                           double* __restrict__ cs) {
+  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
+  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  if (i >= m.nx || j >= m.ny) return;
+  const size_t id = (size_t)j * m.nx + i;
   using Seq = std::make_integer_sequence<int, 27>;
-  out[0] = centre_dot<K, false, 0>(u, Seq{});
-  out[1] = centre_dot<K, false, 1>(u, Seq{});
-  out[2] = centre_dot<K, false, 2>(u, Seq{});
-  out[3] = centre_dot<K, false, 3>(u, Seq{});
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double u0[9], u1[9], u2[9];
+    gstencil<K>(Un, m, c, i, j, u0, u1, u2);
+    double u[27];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      u[l] = u0[l];
+      u[9 + l] = u1[l];
+      u[18 + l] = u2[l];
+    }
+    cs[(size_t)(4 * c + 0) * m.plane + id] = centre_dot<K, false, 0>(u, Seq{});
+    cs[(size_t)(4 * c + 1) * m.plane + id] = centre_dot<K, false, 1>(u, Seq{});
+    cs[(size_t)(4 * c + 2) * m.plane + id] = centre_dot<K, false, 2>(u, Seq{});
+    cs[(size_t)(4 * c + 3) * m.plane + id] = centre_dot<K, false, 3>(u, Seq{});
+  }
+  const Euler<2> ph{m.gamma};
+  bool bad = false;
+  double a[4] = {Un[id], Un[3 * m.plane + id], Un[6 * m.plane + id], Un[9 * m.plane + id]};
+  cs[(size_t)16 * m.plane + id] = ph.speed(0, a, bad);
+  cs[(size_t)17 * m.plane + id] = ph.speed(1, a, bad);
 }
 
-template <int K>
 __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double* __restrict__ Un,
+                                                         const double* __restrict__ cs,
                                                          const double* __restrict__ lam, double dt, double gk,
                                                          double* __restrict__ lamN, double* __restrict__ os) {
   const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
   const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
-  const Euler<2> ph{m.gamma};
-  bool bad = false;
   const size_t id = (size_t)j * m.nx + i;
+  const size_t il = wrap_idx(m, i - 1, j), ir = wrap_idx(m, i + 1, j), ib = wrap_idx(m, i, j - 1),
+               it = wrap_idx(m, i, j + 1);
+  size_t pid[9];
+#pragma unroll
+  for (int p = 0; p < 9; ++p) pid[p] = wrap_idx(m, i - 1 + p % 3, j - 1 + p / 3);
   double Jx[4], Jy[4], jL[4], jB[4], D[4], eps[4], sD[4];
   int pD[4];
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
-    double own[4], lf[4], rt[4], bt[4], tp[4];
-    centres_at<K>(Un, m, c, i, j, own);
-    centres_at<K>(Un, m, c, i - 1, j, lf);
-    centres_at<K>(Un, m, c, i + 1, j, rt);
-    centres_at<K>(Un, m, c, i, j - 1, bt);
-    centres_at<K>(Un, m, c, i, j + 1, tp);
-    jL[c] = own[1] - lf[0];
-    const double jR = rt[1] - own[0];
-    jB[c] = own[3] - bt[2];
-    const double jT = tp[3] - own[2];
+    const double* C = cs + (size_t)(4 * c) * m.plane;
+    jL[c] = C[m.plane + id] - C[il];                              // l(i) - r(i-1)
+    const double jR = C[m.plane + ir] - C[id];                    // l(i+1) - r(i)
+    jB[c] = C[3 * m.plane + id] - C[2 * m.plane + ib];            // b(j) - t(j-1)
+    const double jT = C[3 * m.plane + it] - C[2 * m.plane + id];  // b(j+1) - t(j)
     Jx[c] = fabs(jL[c]) + fabs(jR);
     Jy[c] = fabs(jB[c]) + fabs(jT);
     double v[9];
-    for (int b = 0; b < 3; ++b)
-      for (int a = 0; a < 3; ++a) v[b * 3 + a] = Un[(c * 3) * m.plane + wrap_idx(m, i - 1 + a, j - 1 + b)];
     double S = 0.0, mabs = 0.0;
+#pragma unroll
     for (int p = 0; p < 9; ++p) {
+      v[p] = Un[(c * 3) * m.plane + pid[p]];
       S += v[p];
       mabs = fmax(mabs, fabs(v[p]));
     }
     double best = -1.0;
     int arg = 0;
+#pragma unroll
     for (int p = 0; p < 9; ++p) {
       const double d = fabs(v[p] - S);
       if (d > best) {
@@ -531,27 +614,27 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
   // wave-speed bounds over the patch (first maximal entry)
   double bx = -1.0, by = -1.0;
   int abx = 0, aby = 0;
+#pragma unroll
   for (int p = 0; p < 9; ++p) {
-    const size_t k = wrap_idx(m, i - 1 + p % 3, j - 1 + p / 3);
-    double a[4] = {Un[k], Un[3 * m.plane + k], Un[6 * m.plane + k], Un[9 * m.plane + k]};
-    const double sx = ph.speed(0, a, bad), sy = ph.speed(1, a, bad);
+    const double sx = cs[(size_t)16 * m.plane + pid[p]], sy = cs[(size_t)17 * m.plane + pid[p]];
     if (sx > bx) { bx = sx; abx = p; }
     if (sy > by) { by = sy; aby = p; }
   }
   // sigma per component and its maximum (first maximal component)
   double sgx = -1.0, sgy = -1.0;
   int cx = 0, cy = 0;
-  double sigx[4], sigy[4];
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const bool small = D[c] < eps[c];
-    sigx[c] = small ? 0.0 : gk * Jx[c] / D[c];
-    sigy[c] = small ? 0.0 : gk * Jy[c] / D[c];
-    if (sigx[c] > sgx) { sgx = sigx[c]; cx = c; }
-    if (sigy[c] > sgy) { sgy = sigy[c]; cy = c; }
+    const double sxc = small ? 0.0 : gk * Jx[c] / D[c];
+    const double syc = small ? 0.0 : gk * Jy[c] / D[c];
+    if (sxc > sgx) { sgx = sxc; cx = c; }
+    if (syc > sgy) { sgy = syc; cy = c; }
   }
   const double kx = dt / m.dx, ky = dt / m.dy;
   const double delta = exp(-bx * kx * sgx - by * ky * sgy);
   double dbar = 0.0;
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double l0 = lam[(c * 3) * m.plane + id], l1 = lam[(c * 3 + 1) * m.plane + id],
                  l2 = lam[(c * 3 + 2) * m.plane + id];
@@ -564,27 +647,30 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
   const double bbx = tbar * kx * sgx, bby = tbar * ky * sgy;
   const double sbx = tbar * kx * bx, sby = tbar * ky * by;
   double Jxb[4] = {0, 0, 0, 0}, Jyb[4] = {0, 0, 0, 0}, Db[4] = {0, 0, 0, 0};
-  if (!(D[cx] < eps[cx])) {
-    Jxb[cx] = gk * sbx / D[cx];
-    Db[cx] += -gk * Jx[cx] * sbx / (D[cx] * D[cx]);
+  // (the small-denominator branch has zero derivative)
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c == cx && !(D[c] < eps[c])) {
+      Jxb[c] = gk * sbx / D[c];
+      Db[c] += -gk * Jx[c] * sbx / (D[c] * D[c]);
+    }
+    if (c == cy && !(D[c] < eps[c])) {
+      Jyb[c] = gk * sby / D[c];
+      Db[c] += -gk * Jy[c] * sby / (D[c] * D[c]);
+    }
   }
-  if (!(D[cy] < eps[cy])) {
-    Jyb[cy] = gk * sby / D[cy];
-    Db[cy] += -gk * Jy[cy] * sby / (D[cy] * D[cy]);
-  }
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     os[(size_t)(0 + c) * m.plane + id] = jL[c];
     os[(size_t)(4 + c) * m.plane + id] = jB[c];
     os[(size_t)(8 + c) * m.plane + id] = Jxb[c];
     os[(size_t)(12 + c) * m.plane + id] = Jyb[c];
-    os[(size_t)(16 + c) * m.plane + id] = Db[c];
-    os[(size_t)(20 + c) * m.plane + id] = sD[c];
-    os[(size_t)(24 + c) * m.plane + id] = (double)pD[c];
+    os[(size_t)(16 + c) * m.plane + id] = Db[c] * sD[c];
   }
-  os[(size_t)28 * m.plane + id] = bbx;
-  os[(size_t)29 * m.plane + id] = bby;
-  os[(size_t)30 * m.plane + id] = (double)abx;
-  os[(size_t)31 * m.plane + id] = (double)aby;
+  const int packed = pD[0] | (pD[1] << 4) | (pD[2] << 8) | (pD[3] << 12) | (abx << 16) | (aby << 20);
+  os[(size_t)20 * m.plane + id] = (double)packed;
+  os[(size_t)21 * m.plane + id] = bbx;
+  os[(size_t)22 * m.plane + id] = bby;
 }
 
 // face-centre value adjoints of every cell: [c][r, l, t, b]
@@ -596,6 +682,7 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_b_kernel(AdjMesh m, const double
   const size_t id = (size_t)j * m.nx + i;
   const size_t il = wrap_idx(m, i - 1, j), ir = wrap_idx(m, i + 1, j), ib = wrap_idx(m, i, j - 1),
                it = wrap_idx(m, i, j + 1);
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double jL = os[(size_t)c * m.plane + id], jR = os[(size_t)c * m.plane + ir];
     const double jB = os[(size_t)(4 + c) * m.plane + id], jT = os[(size_t)(4 + c) * m.plane + it];
@@ -612,64 +699,80 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_b_kernel(AdjMesh m, const double
   }
 }
 
-template <int K, int DX, int DY>
-__device__ __forceinline__ void oe_gather_one(const AdjMesh& m, int i, int j, const double* __restrict__ Un,
-                                              const double* __restrict__ os, const double* __restrict__ cb,
-                                              const double* avg, double (&acc)[4][3]) {
-  constexpr int L9 = (1 - DX) + 3 * (1 - DY);
-  const size_t n = wrap_idx(m, i + DX, j + DY);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double b[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) b[f] = cb[(size_t)(c * 4 + f) * m.plane + n];
-    acc[c][0] += cwt_dot<K, false, L9>(b);
-    acc[c][1] += cwt_dot<K, false, 9 + L9>(b);
-    acc[c][2] += cwt_dot<K, false, 18 + L9>(b);
-    const double Db = os[(size_t)(16 + c) * m.plane + n];
-    const double s = os[(size_t)(20 + c) * m.plane + n];
-    const int ps = (int)os[(size_t)(24 + c) * m.plane + n];
-    acc[c][0] += Db * (-s + (ps == L9 ? s : 0.0));
-  }
-  const int ax = (int)os[(size_t)30 * m.plane + n], ay = (int)os[(size_t)31 * m.plane + n];
-  if (ax == L9 || ay == L9) {
-    double gr[4];
-    if (ax == L9) {
-      speed_grad(0, m.gamma, avg, gr);
-      const double bb = os[(size_t)28 * m.plane + n];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c][0] += bb * gr[c];
-    }
-    if (ay == L9) {
-      speed_grad(1, m.gamma, avg, gr);
-      const double bb = os[(size_t)29 * m.plane + n];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c][0] += bb * gr[c];
-    }
-  }
-}
+// gather over the 3x3 neighbours n of each cell q, from an LDS tile of the
+// block's cells and a one-cell ring: the transposed face-centre functionals of
+// n's centre adjoints, and the denominator (-s to every patch cell, +s to p*)
+// and wave-speed (gradient at the argmax cell) routes.
+constexpr int OE_TILE_PLANES = 16 + 4 + 3;   // cb, dJ/dD * s, packed indices + beta adjoints
 
 template <int K>
 __global__ void __launch_bounds__(ADJ_T) oe_adj_c_kernel(AdjMesh m, const double* __restrict__ Un,
                                                          const double* __restrict__ os,
                                                          const double* __restrict__ cb, double* __restrict__ lamN) {
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  __shared__ double sh[OE_TILE_PLANES][GTC];
+  const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
+  const int i0 = blockIdx.x * ADJ_TX, j0 = blockIdx.y * ADJ_TY;
+  const int i = i0 + tx, j = j0 + ty;
+  constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;
+#pragma unroll
+  for (int t = 0; t < NLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+    if (p < GTC) {
+      const int py = p / GT, px = p - py * GT;
+      const size_t src = wrap_idx(m, i0 - 1 + px, j0 - 1 + py);
+#pragma unroll
+      for (int pl = 0; pl < 16; ++pl) sh[pl][p] = cb[(size_t)pl * m.plane + src];
+#pragma unroll
+      for (int pl = 16; pl < OE_TILE_PLANES; ++pl) sh[pl][p] = os[(size_t)pl * m.plane + src];
+    }
+  }
+  __syncthreads();
   if (i >= m.nx || j >= m.ny) return;
   const size_t id = (size_t)j * m.nx + i;
   double avg[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) avg[c] = Un[(c * 3) * m.plane + id];
   double acc[4][3] = {};
-  oe_gather_one<K, -1, -1>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, 0, -1>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, 1, -1>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, -1, 0>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, 0, 0>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, 1, 0>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, -1, 1>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, 0, 1>(m, i, j, Un, os, cb, avg, acc);
-  oe_gather_one<K, 1, 1>(m, i, j, Un, os, cb, avg, acc);
+  double gx[4], gy[4];
+  speed_grad(0, m.gamma, avg, gx);
+  speed_grad(1, m.gamma, avg, gy);
+#pragma unroll 1
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int pos = (ty + 1 + dy) * GT + (tx + 1 + dx);
+      const int L9 = (1 - dx) + 3 * (1 - dy);   // position of q in the patch of n = q + (dx, dy)
+      const int packed = (int)sh[20][pos];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double b[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) b[f] = sh[4 * c + f][pos];
+        switch (L9) {
+#define FAM_CW3(P)                                    \
+  case P:                                             \
+    acc[c][0] += cwt_dot<K, false, P>(b);             \
+    acc[c][1] += cwt_dot<K, false, 9 + P>(b);         \
+    acc[c][2] += cwt_dot<K, false, 18 + P>(b);        \
+    break;
+          FAM_CW3(0) FAM_CW3(1) FAM_CW3(2) FAM_CW3(3) FAM_CW3(4) FAM_CW3(5) FAM_CW3(6) FAM_CW3(7) FAM_CW3(8)
+#undef FAM_CW3
+        }
+        const double ds = sh[16 + c][pos];
+        const int ps = (packed >> (4 * c)) & 15;
+        acc[c][0] += ps == L9 ? 0.0 : -ds;
+      }
+      if (((packed >> 16) & 15) == L9) {
+        const double bb = sh[21][pos];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c][0] += bb * gx[c];
+      }
+      if (((packed >> 20) & 15) == L9) {
+        const double bb = sh[22][pos];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c][0] += bb * gy[c];
+      }
+    }
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -738,6 +841,7 @@ struct FamAdjointScratch {
   double* abar = nullptr;     // coefficient adjoints [4][NCF][cells]
   double* os = nullptr;       // OE record [32][cells]
   double* cb = nullptr;       // face-centre adjoints [4][4][cells]
+  double* cs = nullptr;       // OE pre-pass: face-centre values and wave speeds [18][cells]
   double* partial = nullptr;  // per-block alpha adjoints / functional sums
   double* smax = nullptr;     // alpha_x, alpha_y
   double* Jd = nullptr;
@@ -750,7 +854,7 @@ void fam_adjoint_free(fam_ctx* c) {
   if (!c || !c->adj) return;
   FamAdjointScratch* s = c->adj;
   void* bufs[] = {s->ckpt, s->segbuf, s->ucur, s->lam, s->lamN, s->lam1, s->lam2, s->lam0, s->abar,
-                  s->os, s->cb, s->partial, s->smax, s->Jd, s->apv, s->sidx, s->api};
+                  s->os, s->cb, s->cs, s->partial, s->smax, s->Jd, s->apv, s->sidx, s->api};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete s;
@@ -769,7 +873,8 @@ static fam_status adj_alloc(fam_ctx* c, int ncp, int seg) {
   s->ncp = ncp;
   s->seg = seg;
   const size_t L = c->len * sizeof(double), D = sizeof(double);
-  const size_t nb = ((c->cfg[0].nx + fam::ADJ_TX - 1) / fam::ADJ_TX) * ((c->cfg[0].ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
+  const int nx = c->cfg[0].nx, ny = c->cfg[0].ny;
+  const size_t nb = (size_t)((nx + fam::ADJ_TX - 1) / fam::ADJ_TX) * ((ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
   struct A {
     void** p;
     size_t bytes;
@@ -777,6 +882,7 @@ static fam_status adj_alloc(fam_ctx* c, int ncp, int seg) {
             {(void**)&s->lam, L}, {(void**)&s->lamN, L}, {(void**)&s->lam1, L}, {(void**)&s->lam2, L},
             {(void**)&s->lam0, L}, {(void**)&s->abar, D * 4 * 21 * s->cells},
             {(void**)&s->os, D * fam::OES * s->cells}, {(void**)&s->cb, D * 16 * s->cells},
+            {(void**)&s->cs, D * fam::CS * s->cells},
             {(void**)&s->partial, D * 2 * nb}, {(void**)&s->smax, D * 2}, {(void**)&s->Jd, D},
             {(void**)&s->apv, D * 2 * fam::ALPHA_BLOCKS}, {(void**)&s->sidx, sizeof(int) * 2},
             {(void**)&s->api, sizeof(int) * 2 * fam::ALPHA_BLOCKS}};
@@ -790,7 +896,7 @@ static fam_status adj_alloc(fam_ctx* c, int ncp, int seg) {
 
 template <int K>
 static void rT_apply(fam_ctx* c, const fam::AdjMesh& m, const double* Us, const double* lam_out, double b,
-                     double dt, double* out, int accumulate, hipStream_t st) {
+                     double dt, double* out, int accumulate, double* out2, double b2, int acc2, hipStream_t st) {
   FamAdjointScratch* s = c->adj;
   const dim3 grid((m.nx + fam::ADJ_TX - 1) / fam::ADJ_TX, (m.ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
   const int nb = grid.x * grid.y;
@@ -801,7 +907,7 @@ static void rT_apply(fam_ctx* c, const fam::AdjMesh& m, const double* Us, const 
   hipLaunchKernelGGL((fam::adj_coef_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Us, lam_out, b * dt, s->smax,
                      s->abar, s->partial);
   hipLaunchKernelGGL((fam::adj_gather_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, s->abar, lam_out, b, out,
-                     accumulate);
+                     accumulate, out2, b2, acc2);
   hipLaunchKernelGGL(fam::adj_alpha_route_kernel, dim3(1), dim3(fam::RED_T), 0, st, m, Us, s->partial, nb, s->sidx, out);
 }
 
@@ -810,8 +916,9 @@ static void oe_T_apply(fam_ctx* c, const fam::AdjMesh& m, const double* Un, cons
                        double* lamN, hipStream_t st) {
   FamAdjointScratch* s = c->adj;
   const dim3 grid((m.nx + fam::ADJ_TX - 1) / fam::ADJ_TX, (m.ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
-  hipLaunchKernelGGL((fam::oe_adj_a_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, lam, dt, c->gamma_k, lamN,
-                     s->os);
+  hipLaunchKernelGGL((fam::oe_adj_pre_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, s->cs);
+  hipLaunchKernelGGL(fam::oe_adj_a_kernel, grid, dim3(fam::ADJ_T), 0, st, m, Un, s->cs, lam, dt, c->gamma_k,
+                     lamN, s->os);
   hipLaunchKernelGGL(fam::oe_adj_b_kernel, grid, dim3(fam::ADJ_T), 0, st, m, s->os, s->cb);
   hipLaunchKernelGGL((fam::oe_adj_c_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, s->os, s->cb, lamN);
 }
@@ -830,16 +937,45 @@ static fam_status adjoint_k(fam_ctx* c, const double* U0, int nsteps, double dt,
   const size_t bytes = L * sizeof(double);
   if (hipMemcpyAsync(s->ucur, U0, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return FAM_ERR_DEVICE;
 
-  // forward pass with checkpoints (same kernels and launch path as fam_step)
+  // Records steps n0 .. n1-1 from the state in slot 0 of the segment buffer:
+  // step n keeps (U0, U1, U2, Un) in slot n - n0 and writes its result into the
+  // next slot's U0.  The last step's result (only needed at the end of the run,
+  // need_final) goes to ucur.
+  auto record_segment = [&](int n0, int n1, bool need_final) {
+    reset_steps(c, 0.0, dt);
+    enqueue_alpha_full(c, s->segbuf, 0);
+    for (int n = n0; n < n1; ++n) {
+      double* S0 = s->segbuf + (size_t)(4 * (n - n0)) * L;
+      double *S1 = S0 + L, *S2 = S0 + 2 * L, *SN = S0 + 3 * L;
+      const bool last = n + 1 == n1;
+      double* next = last ? s->ucur : S0 + 4 * L;
+      const int par = (n - n0) & 1;
+      fam::launch_step_begin(c->st, 1, par, dt, 0.0, st);
+      enqueue_stage(c, 0, par, S0, S0, S1, nullptr);
+      enqueue_stage(c, 1, par, S0, S1, S2, nullptr);
+      if (c->oe == FAM_OE_OFF) {
+        if (!last || need_final) enqueue_stage(c, 2, par, S0, S2, next, nullptr);
+      } else {
+        enqueue_stage(c, 2, par, S0, S2, SN, nullptr);
+        if (!last || need_final) enqueue_oe(c, par, SN, next, nullptr);
+      }
+    }
+  };
+
+  // forward pass: checkpoints at the start of every segment but the last, which
+  // is recorded directly (same kernels and launch path as fam_step)
   reset_steps(c, 0.0, dt);
   enqueue_alpha_full(c, s->ucur, 0);
-  for (int n = 0; n < nsteps; ++n) {
+  const int last_n0 = (ncp - 1) * every;
+  for (int n = 0; n < last_n0; ++n) {
     if (n % every == 0)
       if (hipMemcpyAsync(s->ckpt + (size_t)(n / every) * L, s->ucur, bytes, hipMemcpyDeviceToDevice, st) !=
           hipSuccess)
         return FAM_ERR_DEVICE;
     enqueue_step(c, s->ucur, n & 1, dt, 0.0);
   }
+  if (hipMemcpyAsync(s->segbuf, s->ucur, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return FAM_ERR_DEVICE;
+  record_segment(last_n0, nsteps, true);
 
   // seed
   const dim3 grid((m.nx + fam::ADJ_TX - 1) / fam::ADJ_TX, (m.ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
@@ -853,28 +989,12 @@ static fam_status adjoint_k(fam_ctx* c, const double* U0, int nsteps, double dt,
   }
 
   // reverse sweep over the segments
-  const size_t aN = std::min<size_t>((L + 255) / 256, 4096);
   for (int sg = ncp - 1; sg >= 0; --sg) {
     const int n0 = sg * every, n1 = std::min(nsteps, n0 + every);
-    double* U = s->ucur;
-    if (hipMemcpyAsync(U, s->ckpt + (size_t)sg * L, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
-      return FAM_ERR_DEVICE;
-    reset_steps(c, 0.0, dt);
-    enqueue_alpha_full(c, U, 0);
-    for (int n = n0; n < n1; ++n) {
-      double* S0 = s->segbuf + (size_t)(4 * (n - n0)) * L;
-      double *S1 = S0 + L, *S2 = S0 + 2 * L, *SN = S0 + 3 * L;
-      const int par = (n - n0) & 1;
-      if (hipMemcpyAsync(S0, U, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return FAM_ERR_DEVICE;
-      fam::launch_step_begin(c->st, 1, par, dt, 0.0, st);
-      enqueue_stage(c, 0, par, S0, S0, S1, nullptr);
-      enqueue_stage(c, 1, par, S0, S1, S2, nullptr);
-      enqueue_stage(c, 2, par, S0, S2, SN, nullptr);
-      if (c->oe == FAM_OE_OFF) {
-        if (hipMemcpyAsync(U, SN, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return FAM_ERR_DEVICE;
-      } else {
-        enqueue_oe(c, par, SN, U, nullptr);
-      }
+    if (sg < ncp - 1) {
+      if (hipMemcpyAsync(s->segbuf, s->ckpt + (size_t)sg * L, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return FAM_ERR_DEVICE;
+      record_segment(n0, n1, false);
     }
     for (int n = n1 - 1; n >= n0; --n) {
       const double* S0 = s->segbuf + (size_t)(4 * (n - n0)) * L;
@@ -885,13 +1005,14 @@ static fam_status adjoint_k(fam_ctx* c, const double* U0, int nsteps, double dt,
         oe_T_apply<K>(c, m, SN, s->lam, dt, s->lamN, st);
       }
       // stage 2: Un = 1/3 U0 + 2/3 (U2 + dt R(U2))
-      rT_apply<K>(c, m, S2, s->lamN, 2.0 / 3.0, dt, s->lam2, 0, st);
-      hipLaunchKernelGGL(fam::adj_axpy_kernel, dim3(aN), dim3(256), 0, st, L, 1.0 / 3.0, s->lamN, s->lam0, 0);
+      //   lam2 = 2/3 lamN + R^T(U2)(2/3 dt lamN),  lam0 = 1/3 lamN
+      rT_apply<K>(c, m, S2, s->lamN, 2.0 / 3.0, dt, s->lam2, 0, s->lam0, 1.0 / 3.0, 0, st);
       // stage 1: U2 = 3/4 U0 + 1/4 (U1 + dt R(U1))
-      rT_apply<K>(c, m, S1, s->lam2, 0.25, dt, s->lam1, 0, st);
-      hipLaunchKernelGGL(fam::adj_axpy_kernel, dim3(aN), dim3(256), 0, st, L, 0.75, s->lam2, s->lam0, 1);
+      //   lam1 = 1/4 lam2 + R^T(U1)(1/4 dt lam2),  lam0 += 3/4 lam2
+      rT_apply<K>(c, m, S1, s->lam2, 0.25, dt, s->lam1, 0, s->lam0, 0.75, 1, st);
       // stage 0: U1 = U0 + dt R(U0)
-      rT_apply<K>(c, m, S0, s->lam1, 1.0, dt, s->lam0, 1, st);
+      //   lam0 += lam1 + R^T(U0)(dt lam1)
+      rT_apply<K>(c, m, S0, s->lam1, 1.0, dt, s->lam0, 1, nullptr, 0.0, 0, st);
       std::swap(s->lam, s->lam0);
     }
   }

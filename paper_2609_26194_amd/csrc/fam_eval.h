@@ -177,4 +177,50 @@ __device__ __forceinline__ double cwt_dot(const double* b) {
   return acc;
 }
 
+
+// ---------------------------------------------------------------------------
+// Sign-symmetric point groups.  The 32 flux points of a cell form 8 groups of
+// 4 points (sx X, sy Y), sx, sy = +-1, with (X, Y) one of (1/2, GS0), (1/2, GS1)
+// (x-faces), (GS0, 1/2), (GS1, 1/2) (y-faces) and {GS0, GS1}^2 (volume).
+// phi_l(sx X, sy Y) = phi_l(X, Y) sx^(ax_l odd) sy^(ay_l odd): the values at the
+// four points follow from four parity sums of the coefficients, and the
+// transposed evaluation from four signed sums.  Node indices: 0 = GS0,
+// 1 = GS1, 2 = 1/2.  Point s of a group: 0 (+,+), 1 (+,-), 2 (-,+), 3 (-,-).
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ constexpr int parity_class() {
+  return (AX[L] & 1) + 2 * (AY[L] & 1);
+}
+
+template <int L, int NXI, int NYI>
+__device__ __forceinline__ constexpr double phi_node() {
+  return legn(AX[L], NXI) * legn(AY[L], NYI);
+}
+
+template <int NXI, int NYI, int... L>
+__device__ __forceinline__ void parity_sums(const double* cf, double (&P)[4], std::integer_sequence<int, L...>) {
+  P[0] = P[1] = P[2] = P[3] = 0.0;
+  ((P[parity_class<L>()] = fma(cf[L], phi_node<L, NXI, NYI>(), P[parity_class<L>()])), ...);
+}
+
+template <int NXI, int NYI, int... L>
+__device__ __forceinline__ void parity_scatter(double* ab, const double (&Q)[4], std::integer_sequence<int, L...>) {
+  ((ab[L] = fma(phi_node<L, NXI, NYI>(), Q[parity_class<L>()], ab[L])), ...);
+}
+
+// point s of a group: s = 0 (+,+), 1 (+,-), 2 (-,+), 3 (-,-)
+__device__ __forceinline__ constexpr double grp_sx(int s) { return s < 2 ? 1.0 : -1.0; }
+__device__ __forceinline__ constexpr double grp_sy(int s) { return (s & 1) ? -1.0 : 1.0; }
+
+template <int NXI, int NYI, int NCF>
+__device__ __forceinline__ void group_values(const double* cf, double (&v)[4]) {
+  double P[4];
+  parity_sums<NXI, NYI>(cf, P, std::make_integer_sequence<int, NCF>{});
+  const double a = P[0] + P[1], b = P[0] - P[1], c = P[2] + P[3], d = P[2] - P[3];
+  v[0] = a + c;
+  v[1] = a - c;
+  v[2] = b + d;
+  v[3] = b - d;
+}
+
 }  // namespace fam

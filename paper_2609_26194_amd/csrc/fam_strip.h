@@ -1,0 +1,62 @@
+// fam_strip.h - the marching-strip machinery shared by the stage, OE and
+// adjoint kernels: a 64-lane wave owns a strip of columns and marches up a tile
+// of rows, keeping three state rows in an LDS ring.
+#pragma once
+
+#include "fam_device.h"
+#include "fam_kernels.h"
+
+namespace fam {
+
+constexpr int LANES = 64;
+constexpr int NPL = 12;            // planes held in LDS for up to 4 components x 3 moments
+
+// ---------------------------------------------------------------------------
+// LDS row window: lane l holds LDS column l = grid column i0 - 2 + l.  Lanes 0
+// and 63 only load; lanes 1 and 62 are ring columns; lanes 2..61 write output.
+// ---------------------------------------------------------------------------
+struct Window {
+  double v[3][NPL][LANES];
+};
+
+// three row slots used as a ring: row r+2 is fetched into the slot of row r-1
+// once every read of row r-1 in the current iteration is done
+__device__ __forceinline__ int slot_of(int r) { return ((r % 3) + 3) % 3; }
+
+template <int NPLU>
+__device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0, int r,
+                                          int lane, double (&reg)[NPLU]) {
+  const int gj = ghost(r, in.ny, in.bcy);
+  const int gi = ghost(i0 - 2 + lane, in.nx, in.bcx);
+  const size_t base = (size_t)gj * in.nx + gi;
+#pragma unroll
+  for (int p = 0; p < NPLU; ++p) reg[p] = U[p * in.plane + base];
+}
+
+template <int NPLU>
+__device__ __forceinline__ void store_row(Window& W, int slot, int lane, const double (&reg)[NPLU]) {
+#pragma unroll
+  for (int p = 0; p < NPLU; ++p) W.v[slot][p][lane] = reg[p];
+}
+
+// stencil of component c around LDS column col (clamped for the load-only lanes)
+template <int K>
+__device__ __forceinline__ void gather(const Window& W, int c, int col, int sl, int sm, int sh,
+                                       double (&u0)[9], double (&u1)[9], double (&u2)[9]) {
+  const int sr[3] = {sl, sm, sh};
+  const int cm = col > 0 ? col - 1 : 0, cp = col < LANES - 1 ? col + 1 : LANES - 1;
+  const int cc[3] = {cm, col, cp};
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int l = b * 3 + a;
+      u0[l] = W.v[sr[b]][c * 3 + 0][cc[a]];
+      const bool x_used = (K >= 5) ? (l != 1 && l != 7) : (l == 4);
+      const bool y_used = (K >= 5) ? (l != 3 && l != 5) : (l == 4);
+      u1[l] = x_used ? W.v[sr[b]][c * 3 + 1][cc[a]] : 0.0;
+      u2[l] = y_used ? W.v[sr[b]][c * 3 + 2][cc[a]] : 0.0;
+    }
+}
+
+}  // namespace fam
