@@ -89,6 +89,25 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+// minimum density and pressure over the four points of one point group
+template <int NXI, int NYI, int NCF, class P>
+__device__ __forceinline__ void pp_group_min(const P& phys, const double (&cf)[P::NC][NCF], double& rmin,
+                                             double& pmin) {
+  double v[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double g[4];
+    group_values<NXI, NYI, NCF>(cf[c], g);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s][c] = g[s];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    rmin = fmin(rmin, v[s][0]);
+    pmin = fmin(pmin, phys.pressure(v[s], rcp(v[s][0])));
+  }
+}
+
 // Called by all 64 lanes of the wave (uniform control flow).  Each lane first
 // runs a cheap sufficient test; the few cells that fail it (near
 // discontinuities) are then limited one at a time by the whole wave, lane l
@@ -131,6 +150,21 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
         const double plo = (g - 1.0) * (avg[3] - dev[3] - 0.5 * (mm * mm + nn * nn) / rlo);
         if (plo > eps + margin) need = false;
       }
+    }
+    if (__ballot(need) == 0) return;
+    // second test, exact: density and pressure at the 32 flux points (point
+    // groups, all lanes); only cells with a violation are limited below
+    if (need) {
+      double rmin = 1e300, pmin = 1e300;
+      pp_group_min<0, 2, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<1, 2, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<2, 0, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<2, 1, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<0, 0, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<1, 0, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<0, 1, NCF>(phys, cf, rmin, pmin);
+      pp_group_min<1, 1, NCF>(phys, cf, rmin, pmin);
+      need = (rmin < eps) || (pmin < eps);
     }
     unsigned long long todo = __ballot(need);
     if (todo == 0) return;
