@@ -499,6 +499,17 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   double pbx = 0.0, pby = 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) prevTopC[c] = prevJb[c] = pJx[c] = pD[c] = pEps[c] = 0.0;
+  // spectral radii of the rows r - 1, r (carried) and r + 1 of the current row r
+  double spx[3], spy[3];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    double a1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a1[c] = W.v[slot_of(j0 - 2 + q)][c * 3][col];
+    spx[q] = phys.speed(0, a1, bad);
+    spy[q] = phys.speed(1, a1, bad);
+  }
+  spx[2] = spy[2] = 0.0;
 
 #pragma unroll 1
   for (int r = j0 - 1; r <= rend; ++r) {
@@ -552,48 +563,46 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
       prevJb[c] = Jb[c];
       prevTopC[c] = ctr[c][2];
     }
+    // spectral radii of row r + 1 (each cell once; rows r - 1, r carried)
+    {
+      double a1[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) a1[c] = W.v[sh][c * 3][col];
+      spx[2] = phys.speed(0, a1, bad);
+      spy[2] = phys.speed(1, a1, bad);
+    }
     if (!ring_lo) {
-      const int srow[3] = {sl, sm, sh};
-      const int cm = col > 0 ? col - 1 : 0, cp = col < LANES - 1 ? col + 1 : LANES - 1;
-      const int cc[3] = {cm, col, cp};
-      double bx = 0.0, by = 0.0;
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          double avg[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) avg[c] = W.v[srow[b]][c * 3][cc[a]];
-          bx = fmax(bx, phys.speed(0, avg, bad));
-          by = fmax(by, phys.speed(1, avg, bad));
-        }
+      // wave-speed bounds over the 3x3 patch: column maxima, then the neighbours
+      double bx = fmax(fmax(spx[0], spx[1]), spx[2]);
+      double by = fmax(fmax(spy[0], spy[1]), spy[2]);
+      bx = fmax(bx, fmax(__shfl_up(bx, 1, LANES), __shfl_down(bx, 1, LANES)));
+      by = fmax(by, fmax(__shfl_up(by, 1, LANES), __shfl_down(by, 1, LANES)));
       pbx = bx;
       pby = by;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         if (A.type == 2) {
-          double S = 0.0, mabs = 0.0;
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const double v = W.v[srow[b]][c * 3][cc[a]];
-              S += v;
-              mabs = fmax(mabs, fabs(v));
-            }
-          double D = 0.0;
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) D = fmax(D, fabs(W.v[srow[b]][c * 3][cc[a]] - S));
-          pD[c] = D;
-          pEps[c] = 1e-14 * fmax(mabs, 1.0);
+          // S = sum, M = max, m = min of the 3x3 averages (column-wise, then across
+          // the neighbouring lanes); max |v - S| = max(M - S, S - m) and
+          // max |v| = max(|M|, |m|) (rounding is monotone)
+          const double v0 = W.v[sl][c * 3][col], v1 = W.v[sm][c * 3][col], v2 = W.v[sh][c * 3][col];
+          const double cs = v0 + v1 + v2;
+          const double cM = fmax(fmax(v0, v1), v2), cmn = fmin(fmin(v0, v1), v2);
+          const double S = __shfl_up(cs, 1, LANES) + cs + __shfl_down(cs, 1, LANES);
+          const double M = fmax(cM, fmax(__shfl_up(cM, 1, LANES), __shfl_down(cM, 1, LANES)));
+          const double mn = fmin(cmn, fmin(__shfl_up(cmn, 1, LANES), __shfl_down(cmn, 1, LANES)));
+          pD[c] = fmax(M - S, S - mn);
+          pEps[c] = 1e-14 * fmax(fmax(fabs(M), fabs(mn)), 1.0);
         } else {
           pD[c] = A.stats[in.id * 8 + c];       // D_Omega
           pEps[c] = A.stats[in.id * 8 + 4 + c]; // eps_Omega
         }
       }
     }
+    spx[0] = spx[1];
+    spx[1] = spx[2];
+    spy[0] = spy[1];
+    spy[1] = spy[2];
 
     __syncthreads();
     if (pre) store_row<NPLU>(W, slot_of(r + 2), lane, reg);
