@@ -52,6 +52,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--n", type=int, default=2048)
     p.add_argument("--k", type=int, default=5)
+    p.add_argument("--no-main", action="store_true", help="skip the main workload (profiling of the other legs)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-n", type=int, default=512)
     p.add_argument("--cpu-sample-steps", type=int, default=24)
@@ -291,20 +292,11 @@ def adjoint(n, steps, every):
             "forward_ms": t_f * 1e3, "gradient_ms": t_a * 1e3, "gradient_over_forward": t_a / t_f}
 
 
-def main():
-    args = parse()
-    if args.ingest_counters:
-        ingest_counters(*args.ingest_counters)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
-              file=sys.stderr)
-        sys.exit(2)
+def main_workload(args, n, k):
+    """The headline measurement: cell-updates/s of the full step and the stage-kernel roofline."""
     import torch
     import fam_inputs as fi
     from paper_2609_26194_amd import Fam, FamConfig
-
-    n, k = args.n, args.k
     cfg = FamConfig(dim=2, nx=n, ny=n, k=k, system="euler", bc_x="transmissive", bc_y="transmissive",
                     oe="type2", cfl=0.2, pp=True)
     U0 = torch.tensor(fi.four_quadrant(n, 0), dtype=torch.float64).cuda()
@@ -328,7 +320,7 @@ def main():
     roofline = stage_roofline(fam, U, k, cells)
     fam.close()
     copy_calibration()
-    out = {
+    return {
         "metric": "2D Euler FAM cell-updates/s (FP64, k=5)",
         "value": value,
         "unit": "cell-updates/s",
@@ -346,6 +338,21 @@ def main():
                    "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}},
         "roofline": roofline,
     }
+
+
+def main():
+    args = parse()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    n, k = args.n, args.k
+    out = {}
+    if not args.no_main:
+        out = main_workload(args, n, k)
     if not args.no_batched:
         log("batched workload")
         out["batched"] = batched(args.batched_steps)
