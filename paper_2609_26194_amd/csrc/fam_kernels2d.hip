@@ -77,44 +77,39 @@ __device__ __forceinline__ double smallest_root_unit(double a, double b, double 
 }
 
 
-__device__ __forceinline__ double bcast_lane(double x, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
-  return __hiloint2double(hi, lo);
+// min over the 32 lanes of each half of the wave (DPP within rows of 16, then
+// one exchange between the two rows of the half)
+template <int CTRL>
+__device__ __forceinline__ double dpp_min(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return fmin(v, __hiloint2double(hi, lo));
 }
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-  return v;
+__device__ __forceinline__ double half_wave_min(double v) {
+  v = dpp_min<0xB1>(v);    // quad_perm [1,0,3,2]
+  v = dpp_min<0x4E>(v);    // quad_perm [2,3,0,1]
+  v = dpp_min<0x141>(v);   // row_half_mirror
+  v = dpp_min<0x140>(v);   // row_mirror: the row minimum in all 16 lanes
+  return fmin(v, __shfl_xor(v, 16, 64));
 }
 
-// minimum density and pressure over the four points of one point group
-template <int NXI, int NYI, int NCF, class P>
-__device__ __forceinline__ void pp_group_min(const P& phys, const double (&cf)[P::NC][NCF], double& rmin,
-                                             double& pmin) {
-  double v[4][4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double g[4];
-    group_values<NXI, NYI, NCF>(cf[c], g);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s][c] = g[s];
-  }
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    rmin = fmin(rmin, v[s][0]);
-    pmin = fmin(pmin, phys.pressure(v[s], rcp(v[s][0])));
-  }
-}
+// LDS staging of the limiter's exact test: up to 8 cells of a wave at a time
+constexpr int PP_CHUNK = 8;
+struct PPStage {
+  double cf[PP_CHUNK][4 * 21 + 1];   // coefficients of the 4 components, eps
+  double th[PP_CHUNK][2];
+};
 
 // Called by all 64 lanes of the wave (uniform control flow).  Each lane first
 // runs a cheap sufficient test; the few cells that fail it (near
-// discontinuities) are then limited one at a time by the whole wave, lane l
-// evaluating flux point l mod 32 of that cell, so the exact test costs the wave
-// a few hundred instructions per such cell instead of a divergent 32-point loop.
+// discontinuities) are then tested exactly and, where needed, limited: their
+// coefficients go to LDS, and each half of the wave takes one cell, lane l
+// evaluating flux point l mod 32, so a cell costs the wave a few dozen
+// instructions instead of a divergent 32-point loop.
 template <int K, int NCF, int MD, class P>
-__device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NCF], bool& bad, int lane) {
+__device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NCF], bool& bad, int lane,
+                                           PPStage& S) {
   constexpr int NC = P::NC;
   if constexpr (NC != 4) {
     return;
@@ -151,27 +146,12 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
         if (plo > eps + margin) need = false;
       }
     }
-    if (__ballot(need) == 0) return;
-    // second test, exact: density and pressure at the 32 flux points (point
-    // groups, all lanes); only cells with a violation are limited below
-    if (need) {
-      double rmin = 1e300, pmin = 1e300;
-      pp_group_min<0, 2, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<1, 2, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<2, 0, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<2, 1, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<0, 0, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<1, 0, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<0, 1, NCF>(phys, cf, rmin, pmin);
-      pp_group_min<1, 1, NCF>(phys, cf, rmin, pmin);
-      need = (rmin < eps) || (pmin < eps);
-    }
     unsigned long long todo = __ballot(need);
     if (todo == 0) return;
-    // basis values at this lane's flux point: right face (1/2, eta_g), left face
-    // (-1/2, eta_g), top face (xi_g, 1/2), bottom face (xi_g, -1/2), volume
-    // points (xi_a, eta_b) at 16 + 4 b + a
-    const int pt = lane & 31;
+    // this lane's flux point: right face (1/2, eta_g), left face (-1/2, eta_g),
+    // top face (xi_g, 1/2), bottom face (xi_g, -1/2), volume (xi_a, eta_b) at
+    // 16 + 4 b + a
+    const int pt = lane & 31, half = lane >> 5;
     const double nd[4] = {-GS1, -GS0, GS0, GS1};
     double px, py;
     if (pt < 4) { px = 0.5; py = nd[pt]; }
@@ -185,38 +165,65 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
     const double kk = 2.0 / (g - 1.0);
     double th1 = 1.0, th2 = 1.0;
     while (todo) {
-      const int src = __builtin_ctzll(todo);
-      todo &= todo - 1;
-      double v[NC], a[NC];
+      // the next (up to) PP_CHUNK cells
+      unsigned long long chunk = 0, rest = todo;
+      int nchunk = 0;
+      while (rest && nchunk < PP_CHUNK) {
+        chunk |= rest & (~rest + 1ull);
+        rest &= rest - 1ull;
+        ++nchunk;
+      }
+      todo = rest;
+      const bool mine = (chunk >> lane) & 1ull;
+      const int slot = __popcll(chunk & ((1ull << lane) - 1ull));
+      if (mine) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        v[c] = 0.0;
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int l = 0; l < NCF; ++l) v[c] = fma(bcast_lane(cf[c][l], src), phi[l], v[c]);
-        a[c] = bcast_lane(avg[c], src);
+          for (int l = 0; l < NCF; ++l) S.cf[slot][c * NCF + l] = cf[c][l];
+        S.cf[slot][NC * NCF] = eps;
       }
-      const double e = bcast_lane(eps, src);
-      // density: theta1 from the minimum over the 32 points
-      const double rmin = wave_min(v[0]);
-      const double t1 = rmin < e ? (a[0] - e) / (a[0] - rmin) : 1.0;
-      // pressure along avg -> density-limited point value
-      const double rho0 = a[0], m0 = a[1], n0 = a[2], E0 = a[3];
-      const double w0 = rho0 + t1 * (v[0] - rho0);
-      const double w[4] = {w0, v[1], v[2], v[3]};
-      const double pw = phys.pressure(w, 1.0 / w0);
-      double t2 = 1.0;
-      if (pw < e) {
-        const double qc = 2.0 * rho0 * E0 - (m0 * m0 + n0 * n0) - kk * e * rho0;
-        const double rd = w0 - rho0, md = w[1] - m0, nd_ = w[2] - n0, Ed = w[3] - E0;
-        const double qa = 2.0 * rd * Ed - (md * md + nd_ * nd_);
-        const double qb = 2.0 * (rho0 * Ed + rd * E0) - 2.0 * (m0 * md + n0 * nd_) - kk * e * rd;
-        t2 = smallest_root_unit(qa, qb, qc);
+      __syncthreads();
+      for (int p = 0; p < nchunk; p += 2) {
+        const int cell = min(p + half, nchunk - 1);   // an odd count: both halves take the last cell
+        const double* C = S.cf[cell];
+        double v[NC], a[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          v[c] = 0.0;
+#pragma unroll
+          for (int l = 0; l < NCF; ++l) v[c] = fma(C[c * NCF + l], phi[l], v[c]);
+          a[c] = C[c * NCF];
+        }
+        const double e = C[NC * NCF];
+        // density: theta1 from the minimum over the 32 points
+        const double rmin = half_wave_min(v[0]);
+        const double t1 = rmin < e ? (a[0] - e) / (a[0] - rmin) : 1.0;
+        // pressure along avg -> density-limited point value
+        const double rho0 = a[0], m0 = a[1], n0 = a[2], E0 = a[3];
+        const double w0 = rho0 + t1 * (v[0] - rho0);
+        const double w[4] = {w0, v[1], v[2], v[3]};
+        const double pw = phys.pressure(w, 1.0 / w0);
+        double t2 = 1.0;
+        if (pw < e) {
+          const double qc = 2.0 * rho0 * E0 - (m0 * m0 + n0 * n0) - kk * e * rho0;
+          const double rd = w0 - rho0, md = w[1] - m0, nd_ = w[2] - n0, Ed = w[3] - E0;
+          const double qa = 2.0 * rd * Ed - (md * md + nd_ * nd_);
+          const double qb = 2.0 * (rho0 * Ed + rd * E0) - 2.0 * (m0 * md + n0 * nd_) - kk * e * rd;
+          t2 = smallest_root_unit(qa, qb, qc);
+        }
+        t2 = half_wave_min(t2);
+        if (pt == 0) {
+          S.th[cell][0] = t1;
+          S.th[cell][1] = t2;
+        }
       }
-      t2 = wave_min(t2);
-      if (lane == src) {
-        th1 = t1;
-        th2 = t2;
+      __syncthreads();
+      if (mine) {
+        th1 = S.th[slot][0];
+        th2 = S.th[slot][1];
       }
+      __syncthreads();
     }
     if (th1 < 1.0 || th2 < 1.0) {
       const double t0 = th1 * th2;
@@ -235,7 +242,7 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
 // ---------------------------------------------------------------------------
 template <int K, class P, bool PP>
 __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, int i0, int j0, int H,
-                           Window& W, double& amax_x, double& amax_y, bool& bad) {
+                           Window& W, PPStage& PS, double& amax_x, double& amax_y, bool& bad) {
   constexpr int NC = P::NC;
   constexpr int NCF = ncoef2d(K);
   constexpr int MD = maxdeg(K);
@@ -300,7 +307,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
     }
 
     // optional positivity limiter on this cell's reconstruction
-    if constexpr (PP) pp_limiter<K, NCF, MD>(phys, cf, bad, lane);
+    if constexpr (PP) pp_limiter<K, NCF, MD>(phys, cf, bad, lane, PS);
 
     // bottom trace -> y-face flux below the current row: (i, r-1/2)
     double Gb[NC], Gt[NC];
@@ -646,13 +653,14 @@ __device__ __forceinline__ void flush_wave_results(double amax_x, double amax_y,
 template <int K, class P, bool PP>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
+  __shared__ PPStage PS;
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
   double amx = 0.0, amy = 0.0;
   bool bad = false;
   const int i0 = blockIdx.x * STRIP;
   const int j0 = blockIdx.y * H;
-  stage_tile<K, P, PP>(phys, A, in, i0, j0, H, W, amx, amy, bad);
+  stage_tile<K, P, PP>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
 }
 
@@ -660,6 +668,7 @@ template <int K, class P, bool PP>
 __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* __restrict__ insts,
                                                                 const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
+  __shared__ PPStage PS;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
 #pragma unroll 1
@@ -668,7 +677,7 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
     double amx = 0.0, amy = 0.0;
-    stage_tile<K, P, PP>(phys, A, in, it.y, it.z, it.w, W, amx, amy, bad);
+    stage_tile<K, P, PP>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
     flush_wave_results(amx, amy, false, in.alpha_out, A.flag);
   }
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
