@@ -13,9 +13,10 @@ graphs), inputs resident in HBM before the timed region.
 Prints one JSON line with the metric (cell-updates/s), a roofline object for the
 dominant kernel (the RK stage kernel, its launches timed with HIP events on the
 library's own stream), the oracle's CPU throughput on a bounded sample, and two
-sub-measurements: the batched workload (256 uneven instances in one persistent
-launch per stage against one context per instance) and the adjoint workload
-(gradient cost over forward cost at 1024^2, 400 steps, checkpoint every 20).
+sub-measurements: the same workload at k = 6, the batched workload (256 uneven
+instances in one persistent launch per stage against one context per instance)
+and the adjoint workload (gradient cost over forward cost at 1024^2, 400 steps,
+checkpoint every 20).
 
 ``python bench.py --ingest-counters FETCH.csv WRITE.csv`` turns the per-dispatch
 CSVs of two ``rocprofv3 --pmc`` runs of this script (FETCH_SIZE, then
@@ -56,6 +57,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-n", type=int, default=512)
     p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--no-k6", action="store_true", help="skip the k = 6 run of the main workload")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--batched-steps", type=int, default=100)
     p.add_argument("--no-adjoint", action="store_true")
@@ -292,6 +294,32 @@ def adjoint(n, steps, every):
             "forward_ms": t_f * 1e3, "gradient_ms": t_a * 1e3, "gradient_over_forward": t_a / t_f}
 
 
+def k6_leg(n, steps, warmup):
+    """The main workload at k = 6 (same data, limiter, boundaries): cell-updates/s only."""
+    import torch
+    import fam_inputs as fi
+    from paper_2609_26194_amd import Fam, FamConfig
+    cfg = FamConfig(dim=2, nx=n, ny=n, k=6, system="euler", bc_x="transmissive", bc_y="transmissive",
+                    oe="type2", cfl=0.2, pp=True)
+    U0 = torch.tensor(fi.four_quadrant(n, 0), dtype=torch.float64).cuda()
+    fam = Fam(cfg)
+    tuned = fam.autotune(U0)
+    U = U0.clone()
+    if warmup:
+        fam.run(U, 0.0, warmup)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, _ = fam.run(U, 0.0, steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fam.close()
+    return {"workload": f"2D Euler four-quadrant (seed 0) {n}x{n}, FAM k=6, OE Type II (jumps of p6), "
+                        f"transmissive, CFL 0.2, positivity limiter, {done} steps",
+            "cell_updates_per_s": n * n * done / elapsed, "ms_per_step": elapsed / done * 1e3,
+            "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}}
+
+
 def main_workload(args, n, k):
     """The headline measurement: cell-updates/s of the full step and the stage-kernel roofline."""
     import torch
@@ -353,6 +381,9 @@ def main():
     out = {}
     if not args.no_main:
         out = main_workload(args, n, k)
+    if not args.no_main and not args.no_k6:
+        log("k = 6 workload")
+        out["k6"] = k6_leg(n, args.steps, args.warmup)
     if not args.no_batched:
         log("batched workload")
         out["batched"] = batched(args.batched_steps)

@@ -48,9 +48,15 @@ def test_invalid_configurations_are_rejected_without_a_device():
     h = ctypes.c_void_p()
     for bad in (dict(dim=3, nx=8, ny=8), dict(dim=2, nx=8, ny=8, k=7), dict(dim=2, nx=2, ny=8),
                 dict(dim=2, nx=8, ny=8, cfl=0.0), dict(dim=2, nx=8, ny=8, gamma=1.0),
-                dict(dim=2, nx=8, ny=8, x0=1.0, x1=0.0)):
+                dict(dim=2, nx=8, ny=8, x0=1.0, x1=0.0), dict(dim=2, nx=65536, ny=32769),
+                dict(dim=1, nx=2), dict(dim=1, nx=8, pp=True)):
         cfg = FamConfig(**bad)
         assert lib.fam_init(ctypes.byref(cfg.to_c()), None, ctypes.byref(h)) == FAM_ERR_ARG
+    # enum values outside their range
+    for field, value in (("oe", 3), ("bc_x", 2), ("bc_y", -1), ("system", 3)):
+        c = FamConfig(dim=2, nx=8, ny=8).to_c()
+        setattr(c, field, value)
+        assert lib.fam_init(ctypes.byref(c), None, ctypes.byref(h)) == FAM_ERR_ARG
     assert lib.fam_init(None, None, ctypes.byref(h)) == FAM_ERR_ARG
     assert lib.fam_step(None, None, 0.0, None) == FAM_ERR_ARG
     assert lib.fam_run(None, None, 1.0, 0, 0.0, None, None) == FAM_ERR_ARG
