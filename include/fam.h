@@ -156,7 +156,14 @@ fam_status fam_autotune(fam_ctx* ctx, const double* U, int reps, int* choice);
  * J for the built-in functional.  Non-smooth points use one-sided choices:
  * |x|' = sign(x) with sign(0) = 0, maxima pass the derivative to their first
  * maximal entry, the zero-denominator branch of the OE coefficient has zero
- * derivative.  Synchronous.  Single-instance 2D contexts only. */
+ * derivative.  Synchronous.  Supported contexts: one 2D Euler instance,
+ * periodic in x and y, OE off or Type II, no positivity limiter, k = 6 with the
+ * jumps of p_6; any other context returns FAM_ERR_STATE.  FAM_ERR_ARG for NULL
+ * pointers, nsteps < 1, dt <= 0 or checkpoint_every < 1; FAM_ERR_NOMEM when the
+ * checkpoints (ceil(nsteps / checkpoint_every) states) and the segment tape
+ * (4 checkpoint_every states) do not fit; FAM_ERR_NONPHYSICAL if the forward
+ * run meets an inadmissible state.  The scratch is kept for later calls and
+ * freed by fam_destroy. */
 fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
                        int checkpoint_every, const double* dJdUT, double* dJdU0, double* J_out);
 
