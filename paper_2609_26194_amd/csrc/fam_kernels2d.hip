@@ -391,7 +391,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
           double ul[NC], ur[NC], fl[NC], fr[NC];
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            ul[c] = __shfl_up(rt[c][q], 1, LANES);
+            ul[c] = from_left(rt[c][q]);
             ur[c] = lt[c][q];
           }
           phys.flux(0, ul, fl);
@@ -407,8 +407,8 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       double FbR[NC], FtR[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        FbR[c] = __shfl_down(Fb[c], 1, LANES);
-        FtR[c] = __shfl_down(Ft[c], 1, LANES);
+        FbR[c] = from_right(Fb[c]);
+        FtR[c] = from_right(Ft[c]);
       }
       // volume terms: 4x4 Gauss points
       double V1[NC], V2[NC];
@@ -564,8 +564,8 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     // this row: J^x, denominators and wave-speed bounds over the 3x3 patch
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double jl = ctr[c][1] - __shfl_up(ctr[c][0], 1, LANES);
-      const double jr = __shfl_down(jl, 1, LANES);
+      const double jl = ctr[c][1] - from_left(ctr[c][0]);
+      const double jr = from_right(jl);
       pJx[c] = fabs(jl) + fabs(jr);
       prevJb[c] = Jb[c];
       prevTopC[c] = ctr[c][2];
@@ -582,8 +582,8 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
       // wave-speed bounds over the 3x3 patch: column maxima, then the neighbours
       double bx = fmax(fmax(spx[0], spx[1]), spx[2]);
       double by = fmax(fmax(spy[0], spy[1]), spy[2]);
-      bx = fmax(bx, fmax(__shfl_up(bx, 1, LANES), __shfl_down(bx, 1, LANES)));
-      by = fmax(by, fmax(__shfl_up(by, 1, LANES), __shfl_down(by, 1, LANES)));
+      bx = fmax(bx, fmax(from_left(bx), from_right(bx)));
+      by = fmax(by, fmax(from_left(by), from_right(by)));
       pbx = bx;
       pby = by;
 #pragma unroll
@@ -595,9 +595,9 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
           const double v0 = W.v[sl][c * 3][col], v1 = W.v[sm][c * 3][col], v2 = W.v[sh][c * 3][col];
           const double cs = v0 + v1 + v2;
           const double cM = fmax(fmax(v0, v1), v2), cmn = fmin(fmin(v0, v1), v2);
-          const double S = __shfl_up(cs, 1, LANES) + cs + __shfl_down(cs, 1, LANES);
-          const double M = fmax(cM, fmax(__shfl_up(cM, 1, LANES), __shfl_down(cM, 1, LANES)));
-          const double mn = fmin(cmn, fmin(__shfl_up(cmn, 1, LANES), __shfl_down(cmn, 1, LANES)));
+          const double S = from_left(cs) + cs + from_right(cs);
+          const double M = fmax(cM, fmax(from_left(cM), from_right(cM)));
+          const double mn = fmin(cmn, fmin(from_left(cmn), from_right(cmn)));
           pD[c] = fmax(M - S, S - mn);
           pEps[c] = 1e-14 * fmax(fmax(fabs(M), fabs(mn)), 1.0);
         } else {

@@ -59,4 +59,19 @@ __device__ __forceinline__ void gather(const Window& W, int c, int col, int sl, 
     }
 }
 
+// neighbour-lane values by DPP whole-wave shifts (GFX9 wave_shr:1 / wave_shl:1):
+// from_left(x) in lane l is x of lane l - 1, from_right(x) is x of lane l + 1;
+// lane 0 (resp. 63) keeps its own value
+__device__ __forceinline__ double from_left(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x138, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double from_right(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 }  // namespace fam
