@@ -525,32 +525,53 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1);
 
-    double ctr[NC][4];
+    // one pass per component: the face-centre values of row r, the sigma of
+    // row r - 1 (whose top face is this row's bottom face), then row r's J^x,
+    // bottom jump and Type II denominator
+    double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      centre_values<K, FULL>(W, c, col, sl, sm, sh, ctr[c]);
+      double ctr[4];
+      centre_values<K, FULL>(W, c, col, sl, sm, sh, ctr);
+      const double Jb = fabs(ctr[3] - prevTopC[c]);
+      {
+        const double Jy = prevJb[c] + Jb;
+        if (!(pD[c] < pEps[c])) {
+          sx = fmax(sx, A.gamma_k * pJx[c] / pD[c]);
+          sy = fmax(sy, A.gamma_k * Jy / pD[c]);
+        }
+      }
+      if (r < rend) {
+        const double jl = ctr[1] - from_left(ctr[0]);
+        const double jr = from_right(jl);
+        pJx[c] = fabs(jl) + fabs(jr);
+        prevJb[c] = Jb;
+        prevTopC[c] = ctr[2];
+        if (!ring_lo) {
+          if (A.type == 2) {
+            // S = sum, M = max, m = min of the 3x3 averages (column-wise, then
+            // across the neighbouring lanes); max |v - S| = max(M - S, S - m) and
+            // max |v| = max(|M|, |m|) (rounding is monotone)
+            const double v0 = W.v[sl][c * 3][col], v1 = W.v[sm][c * 3][col], v2 = W.v[sh][c * 3][col];
+            const double cs = v0 + v1 + v2;
+            const double cM = fmax(fmax(v0, v1), v2), cmn = fmin(fmin(v0, v1), v2);
+            const double S = from_left(cs) + cs + from_right(cs);
+            const double M = fmax(cM, fmax(from_left(cM), from_right(cM)));
+            const double mn = fmin(cmn, fmin(from_left(cmn), from_right(cmn)));
+            pD[c] = fmax(M - S, S - mn);
+            pEps[c] = 1e-14 * fmax(fmax(fabs(M), fabs(mn)), 1.0);
+          } else {
+            pD[c] = A.stats[in.id * 8 + c];       // D_Omega
+            pEps[c] = A.stats[in.id * 8 + 4 + c]; // eps_Omega
+          }
+        }
+      }
       FAM_SCHED_FENCE();
     }
-
-    double Jb[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) Jb[c] = fabs(ctr[c][3] - prevTopC[c]);
 
     // finish the row below
     if (r - 1 >= j0 && out_lane) {
       const size_t idx = (size_t)(r - 1) * in.nx + i;
-      double sx = 0.0, sy = 0.0;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const double Jy = prevJb[c] + Jb[c];
-        double sgx = 0.0, sgy = 0.0;
-        if (!(pD[c] < pEps[c])) {
-          sgx = A.gamma_k * pJx[c] / pD[c];
-          sgy = A.gamma_k * Jy / pD[c];
-        }
-        sx = fmax(sx, sgx);
-        sy = fmax(sy, sgy);
-      }
       const double delta = exp(-pbx * cx * sx - pby * cy * sy);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -561,15 +582,6 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     }
     if (r == rend) break;
 
-    // this row: J^x, denominators and wave-speed bounds over the 3x3 patch
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const double jl = ctr[c][1] - from_left(ctr[c][0]);
-      const double jr = from_right(jl);
-      pJx[c] = fabs(jl) + fabs(jr);
-      prevJb[c] = Jb[c];
-      prevTopC[c] = ctr[c][2];
-    }
     // spectral radii of row r + 1 (each cell once; rows r - 1, r carried)
     {
       double a1[NC];
@@ -586,25 +598,6 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
       by = fmax(by, fmax(from_left(by), from_right(by)));
       pbx = bx;
       pby = by;
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        if (A.type == 2) {
-          // S = sum, M = max, m = min of the 3x3 averages (column-wise, then across
-          // the neighbouring lanes); max |v - S| = max(M - S, S - m) and
-          // max |v| = max(|M|, |m|) (rounding is monotone)
-          const double v0 = W.v[sl][c * 3][col], v1 = W.v[sm][c * 3][col], v2 = W.v[sh][c * 3][col];
-          const double cs = v0 + v1 + v2;
-          const double cM = fmax(fmax(v0, v1), v2), cmn = fmin(fmin(v0, v1), v2);
-          const double S = from_left(cs) + cs + from_right(cs);
-          const double M = fmax(cM, fmax(from_left(cM), from_right(cM)));
-          const double mn = fmin(cmn, fmin(from_left(cmn), from_right(cmn)));
-          pD[c] = fmax(M - S, S - mn);
-          pEps[c] = 1e-14 * fmax(fmax(fabs(M), fabs(mn)), 1.0);
-        } else {
-          pD[c] = A.stats[in.id * 8 + c];       // D_Omega
-          pEps[c] = A.stats[in.id * 8 + 4 + c]; // eps_Omega
-        }
-      }
     }
     spx[0] = spx[1];
     spx[1] = spx[2];
