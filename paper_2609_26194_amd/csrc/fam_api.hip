@@ -173,7 +173,7 @@ extern "C" void fam_destroy(fam_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   fam_adjoint_free(c);
-  void* bufs[] = {c->W1, c->W2, c->st, c->flag, c->stats, c->partial, c->dmax, c->d_work};
+  void* bufs[] = {c->W1, c->W2, c->st, c->flag, c->stats, c->partial, c->dmax, c->d_work, c->tile_perm, c->tile_work};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (auto& a : c->d_insts)
@@ -219,6 +219,16 @@ extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx*
   c->H = f.dim == 2 ? choose_H(f.nx, f.ny) : 1;
   c->H_oe = c->H;
   fam_status a = alloc_common(c);
+  if (a == FAM_OK && f.dim == 2 && c->pp) {
+    // tile heights are >= 8 rows (or the whole mesh when ny < 8)
+    const int strips = (f.nx + fam::STRIP - 1) / fam::STRIP;
+    c->tile_cap = strips * ((f.ny + 7) / 8);
+    if (hipMalloc(&c->tile_perm, sizeof(int) * c->tile_cap) != hipSuccess ||
+        hipMalloc(&c->tile_work, sizeof(int) * c->tile_cap) != hipSuccess)
+      a = FAM_ERR_NOMEM;
+    if (a == FAM_OK) a = set_stage_H(c, c->H);
+    if (a == FAM_OK && hipStreamSynchronize(c->stream) != hipSuccess) a = FAM_ERR_DEVICE;
+  }
   if (a == FAM_OK) a = init_steps(c);
   if (a == FAM_OK) a = build_inst_tables(c);
   if (a != FAM_OK) {
@@ -326,6 +336,18 @@ void enqueue_alpha_full(fam_ctx* c, const double* U, int parity) {
   fam::launch_alpha2d(c->sys, c->phys, U, c->d_ainst[parity], c->ninst, c->max_cells, c->flag, c->stream);
 }
 
+// Set the stage kernel's tile height of a single 2D instance; with the limiter
+// the tile order restarts from the identity for the new tile count.
+fam_status set_stage_H(fam_ctx* c, int H) {
+  c->H = H;
+  if (!c->tile_perm) return FAM_OK;
+  const fam_config& f = c->cfg[0];
+  const int ntiles = ((f.nx + fam::STRIP - 1) / fam::STRIP) * ((f.ny + H - 1) / H);
+  if (ntiles > c->tile_cap) return FAM_ERR_ARG;
+  fam::launch_tile_identity(c->tile_perm, c->tile_work, ntiles, c->stream);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
                           const double* dt_override) {
   static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -340,6 +362,8 @@ void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double
   A.flag = c->flag;
   A.done = &c->st[0].done;
   A.pp = c->pp;
+  A.tile_perm = c->tile_perm;
+  A.tile_work = c->tile_work;
   if (c->ninst == 1) {
     Inst in = inst_for(c, 0, parity, s);
     if (dt_override) in.dt = dt_override;
@@ -477,7 +501,9 @@ extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* c
     int hs = c->H, ho = c->H_oe;
     for (int H : cand) {
       if (H > ny && H != cand[0]) continue;
-      c->H = c->H_oe = H;
+      r = set_stage_H(c, H);
+      if (r != FAM_OK) return r;
+      c->H_oe = H;
       float ms = 0.0f;
       r = time_launches(c, reps, [&] { enqueue_stage(c, 1, 0, U, U, c->W1, nullptr); }, &ms);
       if (r != FAM_OK) return r;
@@ -488,7 +514,8 @@ extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* c
         if (ms < best_o) { best_o = ms; ho = H; }
       }
     }
-    c->H = hs;
+    r = set_stage_H(c, hs);
+    if (r != FAM_OK) return r;
     c->H_oe = ho;
     if (choice) {
       choice[0] = hs;

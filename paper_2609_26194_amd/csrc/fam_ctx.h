@@ -31,6 +31,11 @@ struct fam_ctx {
   int t1_blocks = 256;
   int H = 32;                  // rows per strip tile of the stage kernel (single instance)
   int H_oe = 32;               // rows per strip tile of the OE kernel (single instance)
+  // single 2D instance with the limiter: tile order of the stage kernel and the
+  // per-tile limiter work of its last launch (tile_cap entries each)
+  int* tile_perm = nullptr;
+  int* tile_work = nullptr;
+  int tile_cap = 0;
   // batched
   fam::Inst* d_insts[2][4] = {};    // [parity][stage 0..2, 3 = OE]
   fam::Inst* d_ainst[2] = {};       // [parity]: alpha_out = stage-0 input slot
@@ -57,6 +62,7 @@ struct fam_ctx {
 };
 
 
+fam_status set_stage_H(fam_ctx* c, int H);
 fam::Inst inst_for(const fam_ctx* c, int i, int parity, int stage);
 fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed);
 void enqueue_alpha_full(fam_ctx* c, const double* U, int parity);

@@ -38,6 +38,11 @@ struct StageArgs {
   int* flag;
   const int* done;
   int pp;                  // positivity limiter on the stage reconstruction (2D Euler)
+  // single-instance limiter launches: tiles run in the order tile_perm (cells
+  // that needed the exact test in the previous launch first); each tile writes
+  // its count of such cells to tile_work
+  const int* tile_perm;
+  int* tile_work;
 };
 
 struct OEArgs {
@@ -68,6 +73,9 @@ struct StepState {
 };
 
 void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, hipStream_t s);
+// tile_perm := tiles with tile_work > 0 first, then the others (both in index order)
+void launch_tile_order(const int* tile_work, int* tile_perm, int ntiles, hipStream_t s);
+void launch_tile_identity(int* tile_perm, int* tile_work, int ntiles, hipStream_t s);
 void launch_oe2d(int k, int sys, const OEArgs& A, const Inst& in, int H, hipStream_t s);
 void launch_stage2d_batched(int k, int sys, const StageArgs& A, const Inst* insts, const int4* work, int nwork,
                             int nblocks, hipStream_t s);

@@ -27,6 +27,7 @@
 // of the reconstruction, J^x, J^y, the Type I / Type II denominator over the 3x3
 // patch; sigma = max over components; delta = exp(-beta^x dt sigma^x/dx -
 // beta^y dt sigma^y/dy); first moments scaled by delta, averages copied.
+#include <algorithm>
 #include <utility>
 
 #include "fam_device.h"
@@ -99,6 +100,7 @@ constexpr int PP_CHUNK = 8;
 struct PPStage {
   double cf[PP_CHUNK][4 * 21 + 1];   // coefficients of the 4 components, eps
   double th[PP_CHUNK][2];
+  int nwork;                         // cells of this tile that needed the exact test
 };
 
 // Called by all 64 lanes of the wave (uniform control flow).  Each lane first
@@ -148,6 +150,7 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
     }
     unsigned long long todo = __ballot(need);
     if (todo == 0) return;
+    if (lane == 0) S.nwork += __popcll(todo);
     // this lane's flux point: right face (1/2, eta_g), left face (-1/2, eta_g),
     // top face (xi_g, 1/2), bottom face (xi_g, -1/2), volume (xi_a, eta_b) at
     // 16 + 4 b + a
@@ -651,10 +654,58 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   const P phys = make_phys<P>(A.phys);
   double amx = 0.0, amy = 0.0;
   bool bad = false;
-  const int i0 = blockIdx.x * STRIP;
-  const int j0 = blockIdx.y * H;
+  int i0, j0, tile = 0;
+  if constexpr (PP) {
+    // 1D grid: tiles in the order of the previous launch's limiter work
+    const int strips = (in.nx + STRIP - 1) / STRIP;
+    tile = A.tile_perm[blockIdx.x];
+    i0 = (tile % strips) * STRIP;
+    j0 = (tile / strips) * H;
+    PS.nwork = 0;
+  } else {
+    i0 = blockIdx.x * STRIP;
+    j0 = blockIdx.y * H;
+  }
   stage_tile<K, P, PP>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
+  if constexpr (PP) {
+    if (threadIdx.x == 0) A.tile_work[tile] = PS.nwork;
+  }
+}
+
+// tile_perm := tiles with tile_work > 0 first, then the others, each group in
+// index order (one block; each thread owns a contiguous chunk)
+__global__ void __launch_bounds__(1024) tile_order_kernel(const int* __restrict__ work, int* __restrict__ perm,
+                                                          int n) {
+  __shared__ int cnt[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (n + nt - 1) / nt;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  int heavy = 0;
+  for (int k = lo; k < hi; ++k) heavy += work[k] > 0;
+  cnt[t] = heavy;
+  __syncthreads();
+  // inclusive scan of the per-thread counts (Hillis-Steele)
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = t >= off ? cnt[t - off] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  const int total = cnt[nt - 1];
+  int h = cnt[t] - heavy;              // heavy tiles before this chunk
+  int l = total + (lo - h);            // light tiles go after all heavy ones
+  for (int k = lo; k < hi; ++k) {
+    if (work[k] > 0) perm[h++] = k;
+    else perm[l++] = k;
+  }
+}
+
+__global__ void tile_identity_kernel(int* __restrict__ perm, int* __restrict__ work, int n) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    perm[k] = k;
+    work[k] = 0;
+  }
 }
 
 template <int K, class P, bool PP>
@@ -810,10 +861,14 @@ __global__ void type1_final_kernel(const double* __restrict__ dmax, Inst in, int
 template <int K, class P>
 static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
-  if (A.pp)
-    hipLaunchKernelGGL((stage2d_kernel<K, P, true>), grid, dim3(LANES), 0, s, A, in, H);
-  else
+  if (A.pp) {
+    const int ntiles = grid.x * grid.y;
+    hipLaunchKernelGGL((stage2d_kernel<K, P, true>), dim3(ntiles), dim3(LANES), 0, s, A, in, H);
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, A.tile_work, const_cast<int*>(A.tile_perm),
+                       ntiles);
+  } else {
     hipLaunchKernelGGL((stage2d_kernel<K, P, false>), grid, dim3(LANES), 0, s, A, in, H);
+  }
 }
 template <int K, class P>
 static void launch_oe2d_t(const OEArgs& A, const Inst& in, int H, hipStream_t s) {
@@ -854,6 +909,10 @@ static void launch_oe2d_b(const OEArgs& A, const Inst* insts, const int4* work, 
 
 void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   FAM_DISPATCH_P(sys, FAM_DISPATCH_K(k, (launch_stage2d_t<KK, PP>(A, in, H, s))));
+}
+void launch_tile_identity(int* tile_perm, int* tile_work, int ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(tile_identity_kernel, dim3(std::min(1024, (ntiles + 255) / 256)), dim3(256), 0, s, tile_perm,
+                     tile_work, ntiles);
 }
 void launch_oe2d(int k, int sys, const OEArgs& A, const Inst& in, int H, hipStream_t s) {
   FAM_DISPATCH_P(sys, FAM_DISPATCH_K(k, (launch_oe2d_t<KK, PP>(A, in, H, s))));
