@@ -258,14 +258,25 @@ static fam_status build_work_list(fam_ctx* c, int Hmax) {
       for (int i0 = 0; i0 < f.nx; i0 += fam::STRIP) work.push_back(make_int4(i, i0, j0, H));
   }
   if (work.size() > c->work_cap) {
-    if (c->d_work) (void)hipFree(c->d_work);
-    c->d_work = nullptr;
+    for (void** p : {(void**)&c->d_work, (void**)&c->tile_perm, (void**)&c->tile_work}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
     c->work_cap = 0;
     if (hipMalloc(&c->d_work, sizeof(int4) * work.size()) != hipSuccess) return FAM_ERR_NOMEM;
+    if (c->pp && (hipMalloc(&c->tile_perm, sizeof(int) * work.size()) != hipSuccess ||
+                  hipMalloc(&c->tile_work, sizeof(int) * work.size()) != hipSuccess))
+      return FAM_ERR_NOMEM;
     c->work_cap = work.size();
   }
   HIP_TRY(hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
   c->nwork = (int)work.size();
+  if (c->pp) {
+    // the limiter's work order restarts from the list order
+    fam::launch_tile_identity(c->tile_perm, c->tile_work, c->nwork, c->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
   c->batch_H = Hmax;
   return FAM_OK;
 }

@@ -31,8 +31,8 @@ struct fam_ctx {
   int t1_blocks = 256;
   int H = 32;                  // rows per strip tile of the stage kernel (single instance)
   int H_oe = 32;               // rows per strip tile of the OE kernel (single instance)
-  // single 2D instance with the limiter: tile order of the stage kernel and the
-  // per-tile limiter work of its last launch (tile_cap entries each)
+  // limiter on: order of the stage kernel's tiles (single instance) or work-list
+  // items (batch), and the limiter work per tile / item of its last launch
   int* tile_perm = nullptr;
   int* tile_work = nullptr;
   int tile_cap = 0;

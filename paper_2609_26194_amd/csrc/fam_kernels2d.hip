@@ -717,12 +717,18 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
   bool bad = false;
 #pragma unroll 1
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-    const int4 it = work[w];              // (instance, i0, j0, H)
+    // limiter on: items in the order of the previous launch's limiter work
+    const int wi = PP ? A.tile_perm[w] : w;
+    const int4 it = work[wi];             // (instance, i0, j0, H)
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
     double amx = 0.0, amy = 0.0;
+    if constexpr (PP) PS.nwork = 0;
     stage_tile<K, P, PP>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
     flush_wave_results(amx, amy, false, in.alpha_out, A.flag);
+    if constexpr (PP) {
+      if (threadIdx.x == 0) A.tile_work[wi] = PS.nwork;
+    }
   }
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
@@ -878,10 +884,12 @@ static void launch_oe2d_t(const OEArgs& A, const Inst& in, int H, hipStream_t s)
 template <int K, class P>
 static void launch_stage2d_b(const StageArgs& A, const Inst* insts, const int4* work, int nwork, int nblocks,
                              hipStream_t s) {
-  if (A.pp)
+  if (A.pp) {
     hipLaunchKernelGGL((stage2d_batched_kernel<K, P, true>), dim3(nblocks), dim3(LANES), 0, s, A, insts, work,
                        nwork);
-  else
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, A.tile_work, const_cast<int*>(A.tile_perm),
+                       nwork);
+  } else
     hipLaunchKernelGGL((stage2d_batched_kernel<K, P, false>), dim3(nblocks), dim3(LANES), 0, s, A, insts, work,
                        nwork);
 }
