@@ -189,7 +189,8 @@ def stage_roofline(fam, U, k, cells, reps=10):
     traffic = stored_traffic()
     return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-            "kernel": f"stage2d_kernel<{k}, Euler<2>, true> (mean of the three RK stage launches)",
+            "kernel": f"stage2d_kernel<{k}, Euler<2>, true> and its tile_order_kernel (mean of the three RK "
+                      f"stage launches)",
             "launch_ms": dur * 1e3, "stage_launch_ms": [avg[s] * 1e3 for s in range(3)],
             "flops_per_cell": stage_flops(k), "algorithmic_bytes_per_launch": bytes_alg,
             "hbm_algorithmic_GBs": gbs, "hbm_algorithmic_frac": gbs / HBM_PEAK_GBS}
