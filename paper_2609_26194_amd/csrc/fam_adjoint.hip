@@ -45,6 +45,10 @@
 namespace fam {
 
 constexpr int ADJ_TX = 16, ADJ_TY = 16, ADJ_T = ADJ_TX * ADJ_TY;
+// a block's cells and a one-cell ring: GT x GT tile positions
+constexpr int GT = ADJ_TX + 2;
+constexpr int GTC = GT * GT;
+constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;   // tile positions per thread (at most two)
 
 struct AdjMesh {
   int nx, ny;
@@ -66,16 +70,39 @@ __device__ __forceinline__ size_t wrap_idx(const AdjMesh& m, int i, int j) {
   return (size_t)wrap1(j, m.ny) * m.nx + wrap1(i, m.nx);
 }
 
-// stencil of component c around cell (i, j) (periodic)
+// periodic image of an index at most one period outside [0, n)
+__device__ __forceinline__ int wrap_near(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// the periodic 3x3 patch around the mesh cell (i, j): its three columns and
+// three row offsets (a mesh holds at most 2^31 cells); id(l) is the flat index
+// of patch cell l, row by row from (i - 1, j - 1): id(4) is the cell, id(3) /
+// id(5) its left / right and id(1) / id(7) its bottom / top neighbour
+struct Patch {
+  unsigned cx[3], ry[3];
+  __device__ __forceinline__ unsigned id(int l) const { return ry[l / 3] + cx[l % 3]; }
+};
+
+__device__ __forceinline__ Patch patch_of(const AdjMesh& m, int i, int j) {
+  Patch P;
+  P.cx[0] = wrap_near(i - 1, m.nx);
+  P.cx[1] = i;
+  P.cx[2] = wrap_near(i + 1, m.nx);
+  P.ry[0] = (unsigned)wrap_near(j - 1, m.ny) * (unsigned)m.nx;
+  P.ry[1] = (unsigned)j * (unsigned)m.nx;
+  P.ry[2] = (unsigned)wrap_near(j + 1, m.ny) * (unsigned)m.nx;
+  return P;
+}
+
+// stencil of component c over the patch P
 template <int K>
-__device__ __forceinline__ void gstencil(const double* __restrict__ U, const AdjMesh& m, int c, int i, int j,
+__device__ __forceinline__ void gstencil(const double* __restrict__ U, const AdjMesh& m, int c, const Patch& P,
                                          double (&u0)[9], double (&u1)[9], double (&u2)[9]) {
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int l = b * 3 + a;
-      const size_t id = wrap_idx(m, i - 1 + a, j - 1 + b);
+      const size_t id = P.id(l);
       u0[l] = U[(c * 3 + 0) * m.plane + id];
       const bool x_used = (K >= 5) ? (l != 1 && l != 7) : (l == 4);
       const bool y_used = (K >= 5) ? (l != 3 && l != 5) : (l == 4);
@@ -188,6 +215,13 @@ __device__ __forceinline__ void load_mu(const double* __restrict__ lam, const Ad
     for (int r = 0; r < 3; ++r) mu[c][r] = scale * lam[(c * 3 + r) * m.plane + id];
 }
 
+__device__ __forceinline__ void tile_mu(const double (&tl)[12][GTC], int pos, double (&mu)[4][3]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) mu[c][r] = tl[c * 3 + r][pos];
+}
+
 // G: group index; for face groups B/T hold [side][c] for the two faces of the group
 // (side 0: sign +1 face, side 1: sign -1 face)
 template <int K, int G>
@@ -258,27 +292,57 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
                                                          double* __restrict__ abar, double* __restrict__ partial) {
   constexpr int NC = 4, NCF = ncoef2d(K);
   __shared__ double red[ADJ_T / 64];
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  // the 12 planes of U and of scale * lam over the block's cells and a one-cell
+  // ring (the kernel's registers allow one block per CU, so the tiles fit)
+  __shared__ double tu[12][GTC];
+  __shared__ double tl[12][GTC];
+  const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
+  const int i0 = blockIdx.x * ADJ_TX, j0 = blockIdx.y * ADJ_TY;
+  const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < m.nx && j < m.ny;
+#pragma unroll
+  for (int t = 0; t < NLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+    if (p < GTC) {
+      const int py = p / GT, px = p - py * GT;
+      const size_t src = wrap_idx(m, i0 - 1 + px, j0 - 1 + py);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
+        tu[q][p] = U[(size_t)q * m.plane + src];
+        tl[q][p] = scale * lam[(size_t)q * m.plane + src];
+      }
+    }
+  }
+  __syncthreads();
   double pax = 0.0, pay = 0.0;
   if (inside) {
     const double g = m.gamma;
     const double ax = alpha[0], ay = alpha[1];
     const double idx_ = 1.0 / m.dx, idy = 1.0 / m.dy;
+    const int base = (ty + 1) * GT + (tx + 1);   // this cell in the tiles
     double cf[NC][NCF];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double u0[9], u1[9], u2[9];
-      gstencil<K>(U, m, c, i, j, u0, u1, u2);
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int l = b * 3 + a, pos = base + (b - 1) * GT + (a - 1);
+          const bool x_used = (K >= 5) ? (l != 1 && l != 7) : (l == 4);
+          const bool y_used = (K >= 5) ? (l != 3 && l != 5) : (l == 4);
+          u0[l] = tu[c * 3 + 0][pos];
+          u1[l] = x_used ? tu[c * 3 + 1][pos] : 0.0;
+          u2[l] = y_used ? tu[c * 3 + 2][pos] : 0.0;
+        }
       double tmp[23];
       coeffs2d<K>(u0, u1, u2, tmp, false);
 #pragma unroll
       for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
     }
-    const size_t id = wrap_idx(m, i, j);
+    const size_t id = (size_t)j * m.nx + i;
     double mu[NC][3];
-    load_mu(lam, m, id, scale, mu);
+    tile_mu(tl, base, mu);
     double ab[NC][NCF];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -288,10 +352,10 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
     // x-faces: side 0 = right face (this cell on the left), side 1 = left face
     {
       double nb[NC][3];
-      load_mu(lam, m, wrap_idx(m, i + 1, j), scale, nb);
+      tile_mu(tl, base + 1, nb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_adj(true, mu[c], nb[c], idx_, B[0][c], T[0][c]);
-      load_mu(lam, m, wrap_idx(m, i - 1, j), scale, nb);
+      tile_mu(tl, base - 1, nb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_adj(true, nb[c], mu[c], idx_, B[1][c], T[1][c]);
     }
@@ -300,10 +364,10 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
     // y-faces: side 0 = top face (this cell below), side 1 = bottom face
     {
       double nb[NC][3];
-      load_mu(lam, m, wrap_idx(m, i, j + 1), scale, nb);
+      tile_mu(tl, base + GT, nb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_adj(false, mu[c], nb[c], idy, B[0][c], T[0][c]);
-      load_mu(lam, m, wrap_idx(m, i, j - 1), scale, nb);
+      tile_mu(tl, base - GT, nb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_adj(false, nb[c], mu[c], idy, B[1][c], T[1][c]);
     }
@@ -336,9 +400,7 @@ __device__ __forceinline__ double rt_apply(const double* a) {
 }
 
 // LDS tile of one component's coefficient adjoints over the block's cells and a
-// one-cell ring (periodic wrap)
-constexpr int GT = ADJ_TX + 2;                 // 18 x 18 tile
-constexpr int GTC = GT * GT;
+// one-cell ring (periodic wrap): GT x GT, defined with the block shape
 
 template <int K>
 __global__ void __launch_bounds__(ADJ_T) adj_gather_kernel(AdjMesh m, const double* __restrict__ abar,
@@ -352,8 +414,7 @@ __global__ void __launch_bounds__(ADJ_T) adj_gather_kernel(AdjMesh m, const doub
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < m.nx && j < m.ny;
   double acc[4][3];
-  // tile positions this thread loads (GTC = 324 > ADJ_T: at most two)
-  constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;
+  // tile positions this thread loads
   size_t src[NLP];
 #pragma unroll
   for (int t = 0; t < NLP; ++t) {
@@ -539,12 +600,13 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_pre_kernel(AdjMesh m, const doub
   const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
   const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
-  const size_t id = (size_t)j * m.nx + i;
+  const Patch P = patch_of(m, i, j);
+  const size_t id = P.id(4);
   using Seq = std::make_integer_sequence<int, 27>;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     double u0[9], u1[9], u2[9];
-    gstencil<K>(Un, m, c, i, j, u0, u1, u2);
+    gstencil<K>(Un, m, c, P, u0, u1, u2);
     double u[27];
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
@@ -571,12 +633,8 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
   const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
   const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
-  const size_t id = (size_t)j * m.nx + i;
-  const size_t il = wrap_idx(m, i - 1, j), ir = wrap_idx(m, i + 1, j), ib = wrap_idx(m, i, j - 1),
-               it = wrap_idx(m, i, j + 1);
-  size_t pid[9];
-#pragma unroll
-  for (int p = 0; p < 9; ++p) pid[p] = wrap_idx(m, i - 1 + p % 3, j - 1 + p / 3);
+  const Patch P = patch_of(m, i, j);
+  const size_t id = P.id(4), il = P.id(3), ir = P.id(5), ib = P.id(1), it = P.id(7);
   double Jx[4], Jy[4], jL[4], jB[4], D[4], eps[4], sD[4];
   int pD[4];
 #pragma unroll
@@ -592,7 +650,7 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
     double S = 0.0, mabs = 0.0;
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
-      v[p] = Un[(c * 3) * m.plane + pid[p]];
+      v[p] = Un[(c * 3) * m.plane + P.id(p)];
       S += v[p];
       mabs = fmax(mabs, fabs(v[p]));
     }
@@ -616,7 +674,7 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
   int abx = 0, aby = 0;
 #pragma unroll
   for (int p = 0; p < 9; ++p) {
-    const double sx = cs[(size_t)16 * m.plane + pid[p]], sy = cs[(size_t)17 * m.plane + pid[p]];
+    const double sx = cs[(size_t)16 * m.plane + P.id(p)], sy = cs[(size_t)17 * m.plane + P.id(p)];
     if (sx > bx) { bx = sx; abx = p; }
     if (sy > by) { by = sy; aby = p; }
   }
@@ -680,8 +738,8 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_b_kernel(AdjMesh m, const double
   const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
   const size_t id = (size_t)j * m.nx + i;
-  const size_t il = wrap_idx(m, i - 1, j), ir = wrap_idx(m, i + 1, j), ib = wrap_idx(m, i, j - 1),
-               it = wrap_idx(m, i, j + 1);
+  const size_t il = (size_t)j * m.nx + wrap_near(i - 1, m.nx), ir = (size_t)j * m.nx + wrap_near(i + 1, m.nx);
+  const size_t ib = (size_t)wrap_near(j - 1, m.ny) * m.nx + i, it = (size_t)wrap_near(j + 1, m.ny) * m.nx + i;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double jL = os[(size_t)c * m.plane + id], jR = os[(size_t)c * m.plane + ir];
