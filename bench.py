@@ -104,15 +104,18 @@ def ingest_counters(fetch_csv, write_csv):
             raise SystemExit(f"no dispatch of a kernel matching {key!r}")
         return [v for n in names for v in d[n]]
 
-    stage_f = pick(fetch, "stage2d_kernel<5")
-    stage_w = pick(write, "stage2d_kernel<5")
+    # the stage kernel that the timed launches use: the segment-list kernel when
+    # the autotuner chose it, else the fixed-height one
+    key = "stage2d_list_kernel<5" if any("stage2d_list_kernel<5" in n for n in fetch) else "stage2d_kernel<5"
+    stage_f = pick(fetch, key)
+    stage_w = pick(write, key)
     copy_f = max(pick(fetch, "Mul"))
     copy_w = max(pick(write, "Mul"))
     kib = COPY_BYTES / 1024.0
     f_scale, w_scale = kib / copy_f, kib / copy_w
     fetch_b = sum(stage_f) / len(stage_f) * 1024.0 * f_scale
     write_b = sum(stage_w) / len(stage_w) * 1024.0 * w_scale
-    rec = {"kernel": "stage2d_kernel<5, Euler<2>, true> (all three RK stages)",
+    rec = {"kernel": f"{key}, Euler<2>...> (all three RK stages)", "kernel_key": key,
            "workload": "2D Euler four-quadrant 2048x2048, k=5, positivity limiter",
            "dispatches": len(stage_f),
            "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
@@ -126,14 +129,15 @@ def ingest_counters(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
-def stored_traffic():
-    """HBM bytes per stage launch from the committed counters, or None if stale."""
+def stored_traffic(key):
+    """HBM bytes per stage launch of kernel `key` from the committed counters, or None if
+    they are stale or were taken on the other stage kernel."""
     try:
         with open(COUNTERS_JSON) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sources_sha256") != stage_sources_hash():
+    if rec.get("kernel_sources_sha256") != stage_sources_hash() or rec.get("kernel_key") != key:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -160,7 +164,7 @@ def cpu_baseline(n, steps):
                       f"({dt:.1f} s)"}
 
 
-def stage_roofline(fam, U, k, cells, reps=10):
+def stage_roofline(fam, U, k, cells, seg_list, reps=10):
     """Per-launch duration of the three RK stage launches, HIP events on the library stream."""
     import torch
     from paper_2609_26194_amd.fam import fam_stage
@@ -186,11 +190,17 @@ def stage_roofline(fam, U, k, cells, reps=10):
     achieved = stage_flops(k) * cells / dur / 1e12
     bytes_alg = sum(STAGE_BYTES.values()) / 3.0 * cells
     gbs = bytes_alg / dur / 1e9
-    traffic = stored_traffic()
+    key = f"stage2d_list_kernel<{k}" if seg_list else f"stage2d_kernel<{k}"
+    traffic = stored_traffic(key)
+    if seg_list:
+        kernel = (f"stage2d_list_kernel<{k}, Euler<2>> and the partition of the next launch's segments "
+                  f"(part_scan_kernel, part_cut_kernel) (mean of the three RK stage launches)")
+    else:
+        kernel = (f"stage2d_kernel<{k}, Euler<2>, true> and its tile_order_kernel (mean of the three RK "
+                  f"stage launches)")
     return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-            "kernel": f"stage2d_kernel<{k}, Euler<2>, true> and its tile_order_kernel (mean of the three RK "
-                      f"stage launches)",
+            "kernel": kernel,
             "launch_ms": dur * 1e3, "stage_launch_ms": [avg[s] * 1e3 for s in range(3)],
             "flops_per_cell": stage_flops(k), "algorithmic_bytes_per_launch": bytes_alg,
             "hbm_algorithmic_GBs": gbs, "hbm_algorithmic_frac": gbs / HBM_PEAK_GBS}
@@ -346,7 +356,7 @@ def main_workload(args, n, k):
     cells = n * n
     value = cells * steps / elapsed
     log("stage launches")
-    roofline = stage_roofline(fam, U, k, cells)
+    roofline = stage_roofline(fam, U, k, cells, seg_list=tuned[0] == 0)
     fam.close()
     copy_calibration()
     return {

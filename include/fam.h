@@ -141,9 +141,21 @@ fam_status fam_check(fam_ctx* ctx);
  * the persistent grid size.  Results are unchanged by the choice (bitwise).
  * The context's stage buffers are overwritten, captured step graphs are
  * dropped, and the device flag is cleared.  choice (host, may be NULL, 2 ints)
- * receives (stage H, OE H) or (batch H, persistent blocks).  Synchronous.
+ * receives (stage H, OE H) or (batch H, persistent blocks); stage H = 0 is the
+ * segment list of a limiter-on context (fam_set_tiling).  Synchronous.
  * FAM_ERR_ARG for a NULL context / state or reps < 1; 1D contexts: no-op. */
 fam_status fam_autotune(fam_ctx* ctx, const double* U, int reps, int* choice);
+
+/* Set the launch shapes of a single 2D instance directly (for example a choice
+ * that fam_autotune returned earlier): stage_H = strip-tile height of the RK
+ * stage kernel, or 0 for the segment list of a limiter-on context (each strip
+ * cut into segments of equal cost, recorded per row by the previous stage
+ * launch; one round of waves); oe_H = tile height of the OE kernel.  Results
+ * are unchanged by the choice (bitwise).  Captured step graphs are dropped.
+ * FAM_ERR_ARG for a NULL context, heights outside [8, ny] (or [1, ny] when ny <
+ * 8) or stage_H = 0 without the limiter (or with more strips than wave slots);
+ * FAM_ERR_STATE for 1D or batched contexts.  Asynchronous. */
+fam_status fam_set_tiling(fam_ctx* ctx, int stage_H, int oe_H);
 
 /* Gradient of a final-time functional J(U_T) with respect to the initial state
  * U0 after nsteps steps with the fixed time step dt (not differentiated), by
@@ -166,6 +178,26 @@ fam_status fam_autotune(fam_ctx* ctx, const double* U, int reps, int* choice);
  * freed by fam_destroy. */
 fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
                        int checkpoint_every, const double* dJdUT, double* dJdU0, double* J_out);
+
+/* Test-only exports (single-instance contexts; FAM_ERR_STATE otherwise; FAM_ERR_ARG
+ * for NULL pointers).  Asynchronous.
+ *
+ * fam_dbg_recon: point values of the stage reconstruction p_k of U (Sec. 2.4;
+ *   eqs. 5 / 6, appendix coefficients; ghost cells per the boundary conditions;
+ *   no positivity limiter) at every cell's flux points.  2D: NP = 32 points per
+ *   cell and component: right face (1/2, eta_g), left face (-1/2, eta_g), top
+ *   face (xi_g, 1/2), bottom face (xi_g, -1/2) for g = 0..3, then the volume
+ *   nodes (xi_a, eta_b) at 16 + 4b + a; 1D: NP = 6: right face, left face, volume
+ *   node xi_a at 2 + a.  Gauss nodes ascending in [-1/2, 1/2].  vals (device,
+ *   caller-owned, nc * NP * cells doubles): vals[((c * NP) + q) * cells + cell].
+ * fam_dbg_oe_factors: the OE damping factor delta = exp(-beta^x dt sigma^x / dx
+ *   - beta^y dt sigma^y / dy) of every cell (Prop. 2.1; eq. 2dOE_system, in 1D
+ *   eq. 1dOE_system), as computed by the OE launch of fam_oe on Un with the time
+ *   step in dt_dev; delta (device, caller-owned, cells doubles) in cell order.
+ *   The launch's state output goes to the context's own scratch.  Un must be a
+ *   caller buffer.  FAM_ERR_STATE with OE off. */
+fam_status fam_dbg_recon(fam_ctx* ctx, const double* U, double* vals);
+fam_status fam_dbg_oe_factors(fam_ctx* ctx, const double* Un, const double* dt_dev, double* delta);
 
 void fam_destroy(fam_ctx* ctx);
 const char* fam_status_str(fam_status s);

@@ -402,6 +402,12 @@ def oe_1d(Un, dt, cfg):
     """OE pass of eq. (1dOE_system) (scalar case: eq. 9)."""
     if cfg.oe == "off":
         return Un
+    delta = oe_delta_1d(Un, dt, cfg)
+    return torch.stack([Un[:, 0], Un[:, 1] * delta], dim=1)
+
+
+def oe_delta_1d(Un, dt, cfg):
+    """Damping factor delta of every cell in the OE pass of eq. (1dOE_system)."""
     phys = cfg.phys
     Upad = pad(Un, cfg)
     monos, coef = _jump_monos_coef(Upad, cfg)               # cells -1..n
@@ -416,14 +422,19 @@ def oe_1d(Un, dt, cfg):
     sig = torch.max(_sigma(J, patch, cfg, stats), dim=0).values
     speeds = torch.stack([phys.speed(patch[:, m], 0) for m in range(3)])
     beta = torch.max(speeds, dim=0).values
-    delta = torch.exp(-beta * dt * sig / cfg.dx)
-    return torch.stack([Un[:, 0], Un[:, 1] * delta], dim=1)
+    return torch.exp(-beta * dt * sig / cfg.dx)
 
 
 def oe_2d(Un, dt, cfg):
     """OE pass of eq. (2dOE_system) with the common factor delta_{i,j}."""
     if cfg.oe == "off":
         return Un
+    delta = oe_delta_2d(Un, dt, cfg)
+    return torch.stack([Un[:, 0], Un[:, 1] * delta, Un[:, 2] * delta], dim=1)
+
+
+def oe_delta_2d(Un, dt, cfg):
+    """Damping factor delta_{i,j} of every cell in the OE pass of eq. (2dOE_system)."""
     phys = cfg.phys
     Upad = pad(Un, cfg)
     monos, coef = _jump_monos_coef(Upad, cfg)                # [C, P, ny+2, nx+2]
@@ -447,12 +458,15 @@ def oe_2d(Un, dt, cfg):
     sy = torch.max(_sigma(Jy, patch, cfg, stats), dim=0).values
     bx = torch.max(torch.stack([phys.speed(patch[:, m], 0) for m in range(9)]), dim=0).values
     by = torch.max(torch.stack([phys.speed(patch[:, m], 1) for m in range(9)]), dim=0).values
-    delta = torch.exp(-bx * dt * sx / cfg.dx - by * dt * sy / cfg.dy)
-    return torch.stack([Un[:, 0], Un[:, 1] * delta, Un[:, 2] * delta], dim=1)
+    return torch.exp(-bx * dt * sx / cfg.dx - by * dt * sy / cfg.dy)
 
 
 def oe(Un, dt, cfg):
     return oe_1d(Un, dt, cfg) if cfg.dim == 1 else oe_2d(Un, dt, cfg)
+
+
+def oe_delta(Un, dt, cfg):
+    return oe_delta_1d(Un, dt, cfg) if cfg.dim == 1 else oe_delta_2d(Un, dt, cfg)
 
 
 # ----------------------------------------------------------------------------

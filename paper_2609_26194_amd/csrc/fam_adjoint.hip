@@ -207,14 +207,6 @@ __device__ __forceinline__ void face_adj(bool xface, const double (&muL)[3], con
   }
 }
 
-__device__ __forceinline__ void load_mu(const double* __restrict__ lam, const AdjMesh& m, size_t id, double scale,
-                                        double (&mu)[4][3]) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) mu[c][r] = scale * lam[(c * 3 + r) * m.plane + id];
-}
-
 __device__ __forceinline__ void tile_mu(const double (&tl)[12][GTC], int pos, double (&mu)[4][3]) {
 #pragma unroll
   for (int c = 0; c < 4; ++c)

@@ -106,6 +106,8 @@ static int choose_H(int nx, int ny) {
   return std::min(H, std::max(ny, 1));
 }
 
+static fam_status init_segments(fam_ctx* c);
+
 static fam_status alloc_common(fam_ctx* c) {
   const size_t bytes = c->len * sizeof(double);
   if (hipMalloc(&c->W1, bytes) != hipSuccess) return FAM_ERR_NOMEM;
@@ -173,7 +175,9 @@ extern "C" void fam_destroy(fam_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   fam_adjoint_free(c);
-  void* bufs[] = {c->W1, c->W2, c->st, c->flag, c->stats, c->partial, c->dmax, c->d_work, c->tile_perm, c->tile_work};
+  void* bufs[] = {c->W1,        c->W2,        c->st,       c->flag, c->stats,    c->partial,  c->dmax,
+                  c->d_work,    c->tile_perm, c->tile_work, c->seg,  c->nseg,     c->row_cost, c->row_pref,
+                  c->part_state};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (auto& a : c->d_insts)
@@ -227,6 +231,7 @@ extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx*
         hipMalloc(&c->tile_work, sizeof(int) * c->tile_cap) != hipSuccess)
       a = FAM_ERR_NOMEM;
     if (a == FAM_OK) a = set_stage_H(c, c->H);
+    if (a == FAM_OK) a = init_segments(c);
     if (a == FAM_OK && hipStreamSynchronize(c->stream) != hipSuccess) a = FAM_ERR_DEVICE;
   }
   if (a == FAM_OK) a = init_steps(c);
@@ -347,6 +352,32 @@ void enqueue_alpha_full(fam_ctx* c, const double* U, int parity) {
   fam::launch_alpha2d(c->sys, c->phys, U, c->d_ainst[parity], c->ninst, c->max_cells, c->flag, c->stream);
 }
 
+// Segment-list mode of a single limiter-on 2D instance: buffers, uniform row
+// costs and the first list.  Not used when the strips outnumber the wave slots.
+static fam_status init_segments(fam_ctx* c) {
+  const fam_config& f = c->cfg[0];
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return FAM_ERR_DEVICE;
+  const int strips = (f.nx + fam::STRIP - 1) / fam::STRIP;
+  c->seg_budget = 4 * cus;   // one stage wave per SIMD
+  if (strips > c->seg_budget || strips > fam::PART_MAX_STRIPS) {
+    c->seg_budget = 0;
+    return FAM_OK;
+  }
+  const size_t rows = (size_t)strips * f.ny;
+  if (hipMalloc(&c->seg, sizeof(int4) * c->seg_budget) != hipSuccess ||
+      hipMalloc(&c->nseg, sizeof(int)) != hipSuccess || hipMalloc(&c->row_cost, sizeof(float) * rows) != hipSuccess ||
+      hipMalloc(&c->row_pref, sizeof(float) * rows) != hipSuccess ||
+      hipMalloc(&c->part_state, fam::partition_state_bytes()) != hipSuccess)
+    return FAM_ERR_NOMEM;
+  fam::launch_fill(c->row_cost, 1.0f, rows, c->stream);
+  fam::launch_partition(c->row_cost, c->row_pref, c->part_state, strips, f.ny, c->seg_budget, c->seg, c->nseg,
+                        c->stream);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
 // Set the stage kernel's tile height of a single 2D instance; with the limiter
 // the tile order restarts from the identity for the new tile count.
 fam_status set_stage_H(fam_ctx* c, int H) {
@@ -360,7 +391,7 @@ fam_status set_stage_H(fam_ctx* c, int H) {
 }
 
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
-                          const double* dt_override) {
+                          const double* dt_override, bool repartition) {
   static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
   static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
   fam::StageArgs A{};
@@ -375,20 +406,31 @@ void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double
   A.pp = c->pp;
   A.tile_perm = c->tile_perm;
   A.tile_work = c->tile_work;
+  A.row_cost = nullptr;
   if (c->ninst == 1) {
     Inst in = inst_for(c, 0, parity, s);
     if (dt_override) in.dt = dt_override;
-    if (c->dim == 1)
+    if (c->dim == 1) {
       fam::launch_stage1d(c->k, c->sys, A, in, c->stream);
-    else
+    } else if (c->stage_list) {
+      const fam_config& f = c->cfg[0];
+      A.row_cost = c->row_cost;
+      fam::launch_stage2d_list(c->k, c->sys, A, in, c->seg, c->nseg, c->seg_budget, c->stream);
+      if (repartition)
+        fam::launch_partition(c->row_cost, c->row_pref, c->part_state, (f.nx + fam::STRIP - 1) / fam::STRIP, f.ny,
+                            c->seg_budget, c->seg, c->nseg, c->stream);
+    } else {
       fam::launch_stage2d(c->k, c->sys, A, in, c->H, c->stream);
+    }
   } else {
     fam::launch_stage2d_batched(c->k, c->sys, A, c->d_insts[parity][s], c->d_work, c->nwork, c->pblocks, c->stream);
   }
 }
 
-void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override) {
+void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override,
+                double* delta_out) {
   fam::OEArgs A{};
+  A.delta_out = delta_out;
   A.phys = c->phys;
   A.Un = Un;
   A.Uout = Uout;
@@ -414,12 +456,13 @@ void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const do
 
 void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_final) {
   fam::launch_step_begin(c->st, c->ninst, parity, dt_fixed, t_final, c->stream);
-  enqueue_stage(c, 0, parity, U, U, c->W1, nullptr);
-  enqueue_stage(c, 1, parity, U, c->W1, c->W2, nullptr);
+  // the segment list (limiter on) is re-cut once per step, from stage 0's row costs
+  enqueue_stage(c, 0, parity, U, U, c->W1, nullptr, true);
+  enqueue_stage(c, 1, parity, U, c->W1, c->W2, nullptr, false);
   if (c->oe == FAM_OE_OFF) {
-    enqueue_stage(c, 2, parity, U, c->W2, U, nullptr);
+    enqueue_stage(c, 2, parity, U, c->W2, U, nullptr, false);
   } else {
-    enqueue_stage(c, 2, parity, U, c->W2, c->W1, nullptr);
+    enqueue_stage(c, 2, parity, U, c->W2, c->W1, nullptr, false);
     enqueue_oe(c, parity, c->W1, U, nullptr);
   }
 }
@@ -470,6 +513,39 @@ extern "C" fam_status fam_oe(fam_ctx* c, const double* Un, double* Uout, const d
   return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
 }
 
+extern "C" fam_status fam_set_tiling(fam_ctx* c, int stage_H, int oe_H) {
+  if (!c) return FAM_ERR_ARG;
+  if (c->dim != 2 || c->ninst != 1) return FAM_ERR_STATE;
+  const int ny = c->cfg[0].ny, hmin = std::min(8, ny);
+  if (oe_H < hmin || oe_H > ny) return FAM_ERR_ARG;
+  if (stage_H == 0 ? c->seg_budget == 0 : (stage_H < hmin || stage_H > ny)) return FAM_ERR_ARG;
+  destroy_graphs(c);
+  c->stage_list = stage_H == 0;
+  if (stage_H > 0) {
+    fam_status r = set_stage_H(c, stage_H);
+    if (r != FAM_OK) return r;
+  }
+  c->H_oe = oe_H;
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+extern "C" fam_status fam_dbg_recon(fam_ctx* c, const double* U, double* vals) {
+  if (!c || !U || !vals) return FAM_ERR_ARG;
+  if (c->ninst != 1) return FAM_ERR_STATE;
+  const Inst in = inst_for(c, 0, 0, 0);
+  fam::launch_dbg_recon(c->dim, c->k, c->nc, U, in, vals, c->stream);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
+extern "C" fam_status fam_dbg_oe_factors(fam_ctx* c, const double* Un, const double* dt_dev, double* delta) {
+  if (!c || !Un || !dt_dev || !delta) return FAM_ERR_ARG;
+  if (c->ninst != 1 || c->oe == FAM_OE_OFF) return FAM_ERR_STATE;
+  if (Un == c->W2) return FAM_ERR_ARG;
+  // the OE launch of fam_oe, its output going to the context's second stage buffer
+  enqueue_oe(c, 0, Un, c->W2, dt_dev, delta);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
 // ---------------------------------------------------------------------------
 // autotuner: times the candidate launch shapes on the caller's state and keeps
 // the fastest.  Single 2D instance: the strip-tile height of the stage kernel
@@ -506,8 +582,23 @@ extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* c
   enqueue_alpha_full(c, U, 0);
   fam::launch_step_begin(c->st, c->ninst, 0, 0.0, 0.0, c->stream);
   if (c->ninst == 1) {
+    c->stage_list = false;
     const int ny = c->cfg[0].ny;
-    const int cand[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64};
+    std::vector<int> cand = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64};
+    // plus the heights whose tile count just fits m whole rounds of the chip's
+    // wave slots (4 SIMDs per CU, one or two waves per SIMD)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    const int strips = (c->cfg[0].nx + fam::STRIP - 1) / fam::STRIP;
+    for (int w = 1; w <= 2; ++w)
+      for (int m = 1; m <= 3; ++m) {
+        const int per = m * cus * 4 * w / strips;   // tiles per strip
+        if (per < 1) continue;
+        const int H = (ny + per - 1) / per;
+        if (H >= 8 && H <= ny && std::find(cand.begin(), cand.end(), H) == cand.end()) cand.push_back(H);
+      }
     float best_s = 1e30f, best_o = 1e30f;
     int hs = c->H, ho = c->H_oe;
     for (int H : cand) {
@@ -525,8 +616,24 @@ extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* c
         if (ms < best_o) { best_o = ms; ho = H; }
       }
     }
-    r = set_stage_H(c, hs);
-    if (r != FAM_OK) return r;
+    // limiter on: the cost-partitioned segment list (reported as height 0)
+    c->stage_list = false;
+    if (c->seg_budget > 0) {
+      c->stage_list = true;
+      float ms = 0.0f;
+      r = time_launches(c, reps, [&] { enqueue_stage(c, 1, 0, U, U, c->W1, nullptr); }, &ms);
+      if (r != FAM_OK) return r;
+      if (ms < best_s) {
+        best_s = ms;
+        hs = 0;
+      } else {
+        c->stage_list = false;
+      }
+    }
+    if (hs > 0) {
+      r = set_stage_H(c, hs);
+      if (r != FAM_OK) return r;
+    }
     c->H_oe = ho;
     if (choice) {
       choice[0] = hs;

@@ -36,6 +36,15 @@ struct fam_ctx {
   int* tile_perm = nullptr;
   int* tile_work = nullptr;
   int tile_cap = 0;
+  // single instance, limiter on: the stage kernel can run over a list of strip
+  // segments cut by the recorded cost of every row (one round of waves)
+  bool stage_list = false;
+  int seg_budget = 0;          // wave slots of the chip for the stage kernel
+  int4* seg = nullptr;         // [seg_budget]
+  int* nseg = nullptr;
+  float* row_cost = nullptr;   // [strips * ny]
+  float* row_pref = nullptr;   // [strips * ny] partition scratch
+  void* part_state = nullptr;  // partition counters and per-strip counts
   // batched
   fam::Inst* d_insts[2][4] = {};    // [parity][stage 0..2, 3 = OE]
   fam::Inst* d_ainst[2] = {};       // [parity]: alpha_out = stage-0 input slot
@@ -67,6 +76,7 @@ fam::Inst inst_for(const fam_ctx* c, int i, int parity, int stage);
 fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed);
 void enqueue_alpha_full(fam_ctx* c, const double* U, int parity);
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
-                   const double* dt_override);
-void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override);
+                   const double* dt_override, bool repartition = true);
+void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override,
+                double* delta_out = nullptr);
 void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_final);

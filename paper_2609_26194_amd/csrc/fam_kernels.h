@@ -43,6 +43,9 @@ struct StageArgs {
   // its count of such cells to tile_work
   const int* tile_perm;
   int* tile_work;
+  // single-instance limiter launches over a segment list: cycles spent on each
+  // row of each strip, row_cost[strip * ny + row] (NULL: not recorded)
+  float* row_cost;
 };
 
 struct OEArgs {
@@ -55,6 +58,7 @@ struct OEArgs {
   const double* stats;     // Type I: [inst*8 + c] D_Omega, [inst*8 + 4 + c] eps_Omega
   int* flag;
   const int* done;
+  double* delta_out;       // single instance, test export: delta per cell (NULL: not written)
 };
 
 // per-instance step bookkeeping (device)
@@ -76,6 +80,20 @@ void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, h
 // tile_perm := tiles with tile_work > 0 first, then the others (both in index order)
 void launch_tile_order(const int* tile_work, int* tile_perm, int ntiles, hipStream_t s);
 void launch_tile_identity(int* tile_perm, int* tile_work, int ntiles, hipStream_t s);
+// limiter-on stage launch over a list of strip segments (x unused, y = first
+// column, z = first row, w = rows; w <= 0: empty), one wave per entry; then the
+// list for the next launch: each strip cut into segments of equal recorded cost,
+// at most `budget` segments in all
+void launch_stage2d_list(int k, int sys, const StageArgs& A, const Inst& in, const int4* seg, const int* nseg,
+                         int budget, hipStream_t s);
+// state: partition_state_bytes() of device memory
+size_t partition_state_bytes();
+void launch_partition(const float* row_cost, float* pref, void* state, int strips, int ny, int budget, int4* seg,
+                      int* nseg, hipStream_t s);
+void launch_fill(float* p, float v, size_t n, hipStream_t s);
+constexpr int PART_MAX_STRIPS = 1024;
+// point values of the stage reconstruction at every cell's flux points (test export)
+void launch_dbg_recon(int dim, int k, int nc, const double* U, const Inst& in, double* vals, hipStream_t s);
 void launch_oe2d(int k, int sys, const OEArgs& A, const Inst& in, int H, hipStream_t s);
 void launch_stage2d_batched(int k, int sys, const StageArgs& A, const Inst* insts, const int4* work, int nwork,
                             int nblocks, hipStream_t s);

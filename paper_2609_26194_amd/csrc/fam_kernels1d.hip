@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(T1) oe1d_kernel(OEArgs A, Inst in) {
       beta = fmax(beta, phys.speed(0, avg, bad));
     }
     const double delta = exp(-beta * dt * sig / in.dx);
+    if (A.delta_out) A.delta_out[i] = delta;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       A.Uout[in.offset + (c * 2) * in.plane + i] = S.u[2 * c][t + 1];

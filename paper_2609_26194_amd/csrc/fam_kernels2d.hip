@@ -284,6 +284,10 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 
 #pragma unroll 1
   for (int r = j0 - 1; r <= rend; ++r) {
+    long long t_row = 0;
+    if constexpr (PP) {
+      if (A.row_cost) t_row = clock64();
+    }
     const bool pre = (r + 2 <= rend + 1);
     if (pre) fetch_row<NPLU>(Us, in, i0, r + 2, lane, reg);
     const bool fin = (r - 1 >= j0) && out_lane;   // this iteration finishes row r-1
@@ -451,6 +455,12 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
     __syncthreads();
     if (pre) store_row<NPLU>(W, slot_of(r + 2), lane, reg);
     __syncthreads();
+    if constexpr (PP) {
+      // the iteration reconstructs (and limits) row r: its cost, for the next
+      // launch's partition (rows of this segment only)
+      if (A.row_cost && lane == 0 && r >= j0 && r < rend)
+        A.row_cost[(size_t)(i0 / STRIP) * in.ny + r] = (float)(clock64() - t_row);
+    }
   }
   __syncthreads();
 }
@@ -576,6 +586,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     if (r - 1 >= j0 && out_lane) {
       const size_t idx = (size_t)(r - 1) * in.nx + i;
       const double delta = exp(-pbx * cx * sx - pby * cy * sy);
+      if (A.delta_out) A.delta_out[idx] = delta;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         Uo[(c * 3 + 0) * in.plane + idx] = W.v[sl][c * 3 + 0][col];
@@ -673,6 +684,8 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   }
 }
 
+constexpr int ORDER_MIN_TILES = 1024;   // 256 CUs x 4 SIMDs, one stage wave each
+
 // tile_perm := tiles with tile_work > 0 first, then the others, each group in
 // index order (one block; each thread owns a contiguous chunk)
 __global__ void __launch_bounds__(1024) tile_order_kernel(const int* __restrict__ work, int* __restrict__ perm,
@@ -706,6 +719,190 @@ __global__ void tile_identity_kernel(int* __restrict__ perm, int* __restrict__ w
     perm[k] = k;
     work[k] = 0;
   }
+}
+
+template <int K, class P>
+__global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const int4* __restrict__ seg,
+                                                    const int* __restrict__ nseg) {
+  __shared__ Window W;
+  __shared__ PPStage PS;
+  if (*A.done) return;
+  if ((int)blockIdx.x >= *nseg) return;
+  const int4 it = seg[blockIdx.x];
+  if (it.w <= 0) return;
+  const P phys = make_phys<P>(A.phys);
+  double amx = 0.0, amy = 0.0;
+  bool bad = false;
+  PS.nwork = 0;
+  stage_tile<K, P, true>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
+  flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
+}
+
+// Segment list for the next limiter-on launch.  Each strip's rows are cut into
+// n_s segments of equal recorded cost; n_s = ceil(C_s / (tau - R)) with C_s the
+// strip's cost, R the cost of a segment's three extra ring rows (three mean
+// rows) and tau the smallest per-segment bound (bisection) for which the
+// segments fit the budget (one wave slot each).  Two launches:
+//   part_scan_kernel (one block per strip): inclusive prefix sums of the row
+//     costs and C_s;
+//   part_cut_kernel (one block per strip): every block repeats the bisection
+//     (same inputs, same operations, same result), takes its strip's n_s and
+//     first list index, and starts segment k at the first row whose inclusive
+//     prefix exceeds k C_s / n_s.
+constexpr int PART_T = 1024;
+
+// strip costs of the partition (device)
+struct PartState {
+  float Cs[PART_MAX_STRIPS];
+};
+
+__global__ void __launch_bounds__(PART_T) part_scan_kernel(const float* __restrict__ cost, float* __restrict__ pref,
+                                                          int ny, PartState* __restrict__ ps) {
+  __shared__ float sh[PART_T / 64];
+  const int t = threadIdx.x, s = blockIdx.x, lane = t & 63, wv = t >> 6;
+  const float* __restrict__ C = cost + (size_t)s * ny;
+  float* __restrict__ P = pref + (size_t)s * ny;
+  // thread t owns rows [t * per, (t + 1) * per)
+  const int per = (ny + PART_T - 1) / PART_T;
+  const int r0 = min(ny, t * per), r1 = min(ny, r0 + per);
+  float own = 0.0f;
+  for (int r = r0; r < r1; ++r) own += C[r];
+  // inclusive scan of the thread sums: waves, then the wave totals
+  float v = own;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const float u = __shfl_up(v, off);
+    if (lane >= off) v += u;
+  }
+  if (lane == 63) sh[wv] = v;
+  __syncthreads();
+  if (wv == 0) {
+    float w = lane < PART_T / 64 ? sh[lane] : 0.0f;
+#pragma unroll
+    for (int off = 1; off < PART_T / 64; off <<= 1) {
+      const float u = __shfl_up(w, off);
+      if (lane >= off) w += u;
+    }
+    if (lane < PART_T / 64) sh[lane] = w;
+  }
+  __syncthreads();
+  const float incl = v + (wv > 0 ? sh[wv - 1] : 0.0f);
+  float run = incl - own;
+  for (int r = r0; r < r1; ++r) {
+    run += C[r];
+    P[r] = run;
+  }
+  if (t == PART_T - 1) ps->Cs[s] = incl;
+}
+
+// Segment counts of all strips for the bound tau (lane-strided over the strips,
+// summed across the wave): every lane returns the same total.
+__device__ __forceinline__ int part_count(const float* sC, int strips, int budget, float R, float tau, int lane) {
+  const float inv = 1.0f / (tau - R);
+  int c = 0;
+  for (int q = lane; q < strips; q += 64) {
+    const float x = sC[q] * inv;
+    c += x > (float)budget ? budget + 1 : max(1, (int)ceilf(x));
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) c += __shfl_xor(c, m);
+  return c;
+}
+
+constexpr int PART_CUT_T = 256;
+constexpr int PART_LDS_ROWS = 8192;   // strips up to this height search an LDS copy
+
+__global__ void __launch_bounds__(PART_CUT_T) part_cut_kernel(const float* __restrict__ pref, int strips, int ny,
+                                                              int budget, const PartState* __restrict__ ps,
+                                                              int4* __restrict__ seg, int* __restrict__ nseg) {
+  __shared__ float sC[PART_MAX_STRIPS];
+  __shared__ float sp[PART_LDS_ROWS];
+  __shared__ int s_n, s_base, s_all;
+  __shared__ float s_Cs;
+  const int t = threadIdx.x, s = blockIdx.x, lane = t & 63;
+  const float* __restrict__ P = pref + (size_t)s * ny;
+  const bool in_lds = ny <= PART_LDS_ROWS;
+  if (in_lds)
+    for (int r = t; r < ny; r += PART_CUT_T) sp[r] = P[r];
+  for (int q = t; q < strips; q += PART_CUT_T) sC[q] = ps->Cs[q];
+  __syncthreads();
+  if (t < 64) {
+    // every block repeats the same bisection (same inputs, same operations)
+    float total = 0.0f, cmax = 0.0f;
+    for (int q = lane; q < strips; q += 64) {
+      total += sC[q];
+      cmax = fmaxf(cmax, sC[q]);
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {   // butterfly: every lane ends with the same sums
+      total += __shfl_xor(total, m);
+      cmax = fmaxf(cmax, __shfl_xor(cmax, m));
+    }
+    const float R = 3.0f * total / ((float)strips * (float)ny);
+    // lo: below any fit (fewer than budget segments cannot hold the total).
+    // hi: a bound that fits -- total / (budget - strips) + R fits in exact
+    // arithmetic (the ceilings add at most one per strip); if rounding spoils
+    // it, one segment per strip (strips <= budget) always fits.
+    float lo = total / (float)budget, hi = 2.0f * cmax + R + 1.0f;
+    if (strips < budget) {
+      const float h1 = 1.001f * total / (float)(budget - strips) + R;
+      if (h1 < hi && part_count(sC, strips, budget, R, h1, lane) <= budget) hi = h1;
+    }
+    for (int it = 0; it < 14; ++it) {
+      const float tau = 0.5f * (lo + hi);
+      const bool fits = tau > R && part_count(sC, strips, budget, R, tau, lane) <= budget;
+      if (fits) hi = tau;
+      else lo = tau;
+    }
+    // this strip's count, the counts of the strips before it, and all
+    const float inv = 1.0f / (hi - R);
+    int before = 0, all = 0, mine = 0;
+    for (int q = lane; q < strips; q += 64) {
+      const float x = sC[q] * inv;
+      const int n = max(1, (int)ceilf(x));   // <= budget at a bound that fits
+      all += n;
+      if (q < s) before += n;
+      if (q == s) mine = n;
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      all += __shfl_xor(all, m);
+      before += __shfl_xor(before, m);
+      mine += __shfl_xor(mine, m);
+    }
+    if (lane == 0) {
+      s_n = mine;
+      s_base = before;
+      s_all = all;
+      s_Cs = sC[s];
+    }
+  }
+  __syncthreads();
+  const int n = s_n, b0 = s_base;
+  const float Cs = s_Cs;
+  if (s == 0 && t == 0) *nseg = s_all;
+  for (int k = t; k < n; k += PART_CUT_T) {
+    int st[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int kk = k + e;
+      if (kk == 0) { st[e] = 0; continue; }
+      if (kk == n) { st[e] = ny; continue; }
+      const float target = Cs * (float)kk / (float)n;
+      int x = 0, y = ny;   // first row with P > target
+      while (x < y) {
+        const int m = (x + y) >> 1;
+        if ((in_lds ? sp[m] : P[m]) <= target) x = m + 1;
+        else y = m;
+      }
+      st[e] = x;
+    }
+    seg[b0 + k] = make_int4(0, s * STRIP, st[0], st[1] - st[0]);
+  }
+}
+
+__global__ void fill_kernel(float* __restrict__ p, float v, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = v;
 }
 
 template <int K, class P, bool PP>
@@ -870,8 +1067,11 @@ static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStrea
   if (A.pp) {
     const int ntiles = grid.x * grid.y;
     hipLaunchKernelGGL((stage2d_kernel<K, P, true>), dim3(ntiles), dim3(LANES), 0, s, A, in, H);
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, A.tile_work, const_cast<int*>(A.tile_perm),
-                       ntiles);
+    // up to one tile per wave slot of the chip every tile starts at once: the
+    // order stays the identity set with the tile height
+    if (ntiles > ORDER_MIN_TILES)
+      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, A.tile_work, const_cast<int*>(A.tile_perm),
+                         ntiles);
   } else {
     hipLaunchKernelGGL((stage2d_kernel<K, P, false>), grid, dim3(LANES), 0, s, A, in, H);
   }
@@ -917,6 +1117,32 @@ static void launch_oe2d_b(const OEArgs& A, const Inst* insts, const int4* work, 
 
 void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   FAM_DISPATCH_P(sys, FAM_DISPATCH_K(k, (launch_stage2d_t<KK, PP>(A, in, H, s))));
+}
+template <int K, class P>
+static void launch_stage2d_list_t(const StageArgs& A, const Inst& in, const int4* seg, const int* nseg, int budget,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL((stage2d_list_kernel<K, P>), dim3(budget), dim3(LANES), 0, s, A, in, seg, nseg);
+}
+void launch_stage2d_list(int k, int sys, const StageArgs& A, const Inst& in, const int4* seg, const int* nseg,
+                         int budget, hipStream_t s) {
+  // the limiter is a 2D Euler option
+  (void)sys;
+  switch (k) {
+    case 3: launch_stage2d_list_t<3, Euler<2>>(A, in, seg, nseg, budget, s); break;
+    case 4: launch_stage2d_list_t<4, Euler<2>>(A, in, seg, nseg, budget, s); break;
+    case 5: launch_stage2d_list_t<5, Euler<2>>(A, in, seg, nseg, budget, s); break;
+    default: launch_stage2d_list_t<6, Euler<2>>(A, in, seg, nseg, budget, s); break;
+  }
+}
+size_t partition_state_bytes() { return sizeof(PartState); }
+void launch_partition(const float* row_cost, float* pref, void* state, int strips, int ny, int budget, int4* seg,
+                      int* nseg, hipStream_t s) {
+  PartState* ps = static_cast<PartState*>(state);
+  hipLaunchKernelGGL(part_scan_kernel, dim3(strips), dim3(PART_T), 0, s, row_cost, pref, ny, ps);
+  hipLaunchKernelGGL(part_cut_kernel, dim3(strips), dim3(PART_CUT_T), 0, s, pref, strips, ny, budget, ps, seg, nseg);
+}
+void launch_fill(float* p, float v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<size_t>(1024, (n + 255) / 256)), dim3(256), 0, s, p, v, n);
 }
 void launch_tile_identity(int* tile_perm, int* tile_work, int ntiles, hipStream_t s) {
   hipLaunchKernelGGL(tile_identity_kernel, dim3(std::min(1024, (ntiles + 255) / 256)), dim3(256), 0, s, tile_perm,

@@ -110,6 +110,9 @@ def load_library():
         "fam_check": (I, [VP]),
         "fam_adjoint": (I, [VP, VP, I, D, I, VP, VP, P]),
         "fam_autotune": (I, [VP, VP, I, ctypes.POINTER(I)]),
+        "fam_set_tiling": (I, [VP, I, I]),
+        "fam_dbg_recon": (I, [VP, VP, VP]),
+        "fam_dbg_oe_factors": (I, [VP, VP, VP, VP]),
         "fam_destroy": (None, [VP]),
         "fam_status_str": (ctypes.c_char_p, [I]),
     }
@@ -184,6 +187,18 @@ def fam_stage(h, s, U0, Us, Uout, dt_dev):
 
 def fam_oe(h, Un, Uout, dt_dev):
     _check(load_library().fam_oe(h, _ptr(Un), _ptr(Uout), _ptr(dt_dev)), "fam_oe")
+
+
+def fam_set_tiling(h, stage_H, oe_H):
+    _check(load_library().fam_set_tiling(h, int(stage_H), int(oe_H)), "fam_set_tiling")
+
+
+def fam_dbg_recon(h, U, vals):
+    _check(load_library().fam_dbg_recon(h, _ptr(U), _ptr(vals)), "fam_dbg_recon")
+
+
+def fam_dbg_oe_factors(h, Un, dt_dev, delta):
+    _check(load_library().fam_dbg_oe_factors(h, _ptr(Un), _ptr(dt_dev), _ptr(delta)), "fam_dbg_oe_factors")
 
 
 def fam_check(h):
@@ -299,6 +314,32 @@ class Fam:
 
     def check(self):
         return self._call(fam_check)
+
+    def set_tiling(self, stage_H, oe_H):
+        """Launch shapes of a single 2D instance (stage_H = 0: the limiter's segment list)."""
+        return self._call(fam_set_tiling, stage_H, oe_H)
+
+    def _cells_shape(self):
+        c = self.cfgs[0]
+        return (c.ny, c.nx) if c.dim == 2 else (c.nx,)
+
+    def dbg_recon(self, U):
+        """Point values of the stage reconstruction at every cell's flux points (test export):
+        [ncomp, 32, ny, nx] in 2D, [ncomp, 6, nx] in 1D (point order as in fam.h)."""
+        self._state(U)
+        c = self.cfgs[0]
+        npts = 32 if c.dim == 2 else 6
+        vals = torch.empty((c.ncomp, npts) + self._cells_shape(), dtype=torch.float64, device=self.device)
+        self._call(fam_dbg_recon, U, vals)
+        return vals
+
+    def dbg_oe_factors(self, Un, dt_dev):
+        """OE damping factor delta of every cell for Un and the time step in dt_dev (test export)."""
+        self._state(Un)
+        self._dt(dt_dev)
+        delta = torch.empty(self._cells_shape(), dtype=torch.float64, device=self.device)
+        self._call(fam_dbg_oe_factors, Un, dt_dev, delta)
+        return delta
 
     def autotune(self, U, reps=5):
         """Pick the fastest launch shapes for this context on state U (read only)."""

@@ -20,7 +20,7 @@ import torch
 import fam_inputs as fi
 from oracle import physics
 from oracle.physics import NonPhysicalState, gauss4
-from oracle.scheme import Config, oe, pad, points_2d, point_values, pp_apply, pp_theta, \
+from oracle.scheme import Config, oe, oe_delta, pad, points_2d, point_values, pp_apply, pp_theta, \
     reconstruct, residual, rk3, run, step
 
 
@@ -71,6 +71,21 @@ def test_oe_invariants_2d(k):
     assert bool((err <= 1e-15 * torch.abs(Un[:, 1:])).all())
     # strong jumps are damped somewhere
     assert float(r.min()) < 0.99
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_oe_delta_is_the_factor_oe_applies(dim):
+    """oe_delta returns the per-cell factor that oe multiplies both first moments by."""
+    if dim == 2:
+        cfg = euler2d(20, bc_x="transmissive", bc_y="transmissive")
+        U = torch.tensor(fi.four_quadrant(20, 3))
+    else:
+        cfg = Config(dim=1, nx=200, x0=-5.0, x1=5.0, k=5, system="euler", bc_x="transmissive", oe="type1")
+        U = torch.tensor(fi.shu_osher(200))
+    d = oe_delta(U, 2e-3, cfg)
+    assert d.shape == U.shape[2:]
+    assert bool((d > 0).all()) and bool((d <= 1).all()) and float(d.min()) < 0.99
+    assert torch.equal(oe(U, 2e-3, cfg)[:, 1:], U[:, 1:] * d)
 
 
 def test_oe_invariants_1d():
