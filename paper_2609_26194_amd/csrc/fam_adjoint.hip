@@ -331,6 +331,7 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
       coeffs2d<K>(u0, u1, u2, tmp, false);
 #pragma unroll
       for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
+      __builtin_amdgcn_sched_barrier(0);
     }
     const size_t id = (size_t)j * m.nx + i;
     double mu[NC][3];
@@ -352,7 +353,9 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
       for (int c = 0; c < NC; ++c) face_adj(true, nb[c], mu[c], idx_, B[1][c], T[1][c]);
     }
     coef_group<K, 0>(g, cf, ab, mu, idx_, idy, B, T, ax, pax);
+    __builtin_amdgcn_sched_barrier(0);
     coef_group<K, 1>(g, cf, ab, mu, idx_, idy, B, T, ax, pax);
+    __builtin_amdgcn_sched_barrier(0);
     // y-faces: side 0 = top face (this cell below), side 1 = bottom face
     {
       double nb[NC][3];
@@ -364,11 +367,17 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
       for (int c = 0; c < NC; ++c) face_adj(false, nb[c], mu[c], idy, B[1][c], T[1][c]);
     }
     coef_group<K, 2>(g, cf, ab, mu, idx_, idy, B, T, ay, pay);
+    __builtin_amdgcn_sched_barrier(0);
     coef_group<K, 3>(g, cf, ab, mu, idx_, idy, B, T, ay, pay);
+    __builtin_amdgcn_sched_barrier(0);
     coef_group<K, 4>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    __builtin_amdgcn_sched_barrier(0);
     coef_group<K, 5>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    __builtin_amdgcn_sched_barrier(0);
     coef_group<K, 6>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    __builtin_amdgcn_sched_barrier(0);
     coef_group<K, 7>(g, cf, ab, mu, idx_, idy, B, T, 0.0, pax);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
