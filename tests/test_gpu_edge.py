@@ -103,3 +103,24 @@ def test_state_planes_beyond_2_31_values_tiled_periodic():
     log(f"  bitwise equal to the tiled {P}x{P} result: {same}")
     assert same
     big.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (70, 3), (3, 70), (125, 9)])
+@pytest.mark.parametrize("stage_H", [None, 0])
+def test_limiter_on_small_meshes(nx, ny, stage_H):
+    """The positivity limiter with the default tiling and with the cost-partitioned segment
+    list on meshes smaller than a tile; four-quadrant data whose jumps trip the limiter."""
+    log(f"limiter {nx}x{ny}, stage tiling {'default' if stage_H is None else 'segment list'}")
+    ora, cfg = both_configs(dim=2, nx=nx, ny=ny, k=5, system="euler", bc_x="transmissive", bc_y="periodic",
+                            oe="type2", cfl=0.2, pp=True)
+    U0 = fi.four_quadrant(nx, 3, ny=ny) if nx % 2 == 0 and ny % 2 == 0 else fi.random_euler_state_2d(nx, ny, 8, amp=0.6)
+    ref, _, _ = S.run(torch.tensor(U0), ora, nsteps=4)
+    fam = _fam(cfg)
+    if stage_H is not None:
+        fam.set_tiling(stage_H, min(8, ny))
+    U = to_dev(U0)
+    fam.run(U, 0.0, 4)
+    fam.check()
+    err = rel_linf(U, ref)
+    log(f"  rel Linf {err:.3e}")
+    assert err <= TOL
