@@ -227,7 +227,7 @@ extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx*
     // tile heights are >= 8 rows (or the whole mesh when ny < 8)
     const int strips = (f.nx + fam::STRIP - 1) / fam::STRIP;
     c->tile_cap = strips * ((f.ny + 7) / 8);
-    if (hipMalloc(&c->tile_perm, sizeof(int) * c->tile_cap) != hipSuccess ||
+    if (hipMalloc(&c->tile_perm, sizeof(int) * (c->tile_cap + 1)) != hipSuccess ||
         hipMalloc(&c->tile_work, sizeof(int) * c->tile_cap) != hipSuccess)
       a = FAM_ERR_NOMEM;
     if (a == FAM_OK) a = set_stage_H(c, c->H);
@@ -269,7 +269,7 @@ static fam_status build_work_list(fam_ctx* c, int Hmax) {
     }
     c->work_cap = 0;
     if (hipMalloc(&c->d_work, sizeof(int4) * work.size()) != hipSuccess) return FAM_ERR_NOMEM;
-    if (c->pp && (hipMalloc(&c->tile_perm, sizeof(int) * work.size()) != hipSuccess ||
+    if (c->pp && (hipMalloc(&c->tile_perm, sizeof(int) * (work.size() + 1)) != hipSuccess ||
                   hipMalloc(&c->tile_work, sizeof(int) * work.size()) != hipSuccess))
       return FAM_ERR_NOMEM;
     c->work_cap = work.size();
@@ -362,12 +362,12 @@ static fam_status init_segments(fam_ctx* c) {
     return FAM_ERR_DEVICE;
   const int strips = (f.nx + fam::STRIP - 1) / fam::STRIP;
   c->seg_budget = 4 * cus;   // one stage wave per SIMD
-  if (strips > c->seg_budget || strips > fam::PART_MAX_STRIPS) {
+  if (strips > c->seg_budget || strips > fam::PART_MAX_STRIPS || c->seg_budget > fam::PART_MAX_SEGMENTS) {
     c->seg_budget = 0;
     return FAM_OK;
   }
   const size_t rows = (size_t)strips * f.ny;
-  if (hipMalloc(&c->seg, sizeof(int4) * c->seg_budget) != hipSuccess ||
+  if (hipMalloc(&c->seg, sizeof(int4) * 2 * c->seg_budget) != hipSuccess ||   // the list, then its cut order
       hipMalloc(&c->nseg, sizeof(int)) != hipSuccess || hipMalloc(&c->row_cost, sizeof(float) * rows) != hipSuccess ||
       hipMalloc(&c->row_pref, sizeof(float) * rows) != hipSuccess ||
       hipMalloc(&c->part_state, fam::partition_state_bytes()) != hipSuccess)

@@ -669,13 +669,29 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   if constexpr (PP) {
     // 1D grid: tiles in the order of the previous launch's limiter work
     const int strips = (in.nx + STRIP - 1) / STRIP;
-    tile = A.tile_perm[blockIdx.x];
+    // tiles with limiter work first (spread over the XCDs in turn), then the
+    // others in the XCD-aware order of their row-major index
+    const int N = gridDim.x, L = blockIdx.x, nh = A.tile_perm[N];
+    int idx = L;
+    if (L >= nh) {
+      const int x = L % NXCD;
+      int base = 0, first = 0;
+      for (int q = 0; q <= x; ++q) {
+        const int f = nh + ((q - nh) % NXCD + NXCD) % NXCD;   // first light position on XCD q
+        const int cnt = f < N ? (N - 1 - f) / NXCD + 1 : 0;
+        if (q < x) base += cnt;
+        else first = f;
+      }
+      idx = nh + base + (L - first) / NXCD;
+    }
+    tile = A.tile_perm[idx];
     i0 = (tile % strips) * STRIP;
     j0 = (tile / strips) * H;
     PS.nwork = 0;
   } else {
-    i0 = blockIdx.x * STRIP;
-    j0 = blockIdx.y * H;
+    const int T = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    i0 = (T % gridDim.x) * STRIP;
+    j0 = (T / gridDim.x) * H;
   }
   stage_tile<K, P, PP>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
@@ -706,6 +722,7 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(const int* __restrict_
     __syncthreads();
   }
   const int total = cnt[nt - 1];
+  if (t == 0) perm[n] = total;         // heavy tiles: read by the stage kernel
   int h = cnt[t] - heavy;              // heavy tiles before this chunk
   int l = total + (lo - h);            // light tiles go after all heavy ones
   for (int k = lo; k < hi; ++k) {
@@ -715,9 +732,9 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(const int* __restrict_
 }
 
 __global__ void tile_identity_kernel(int* __restrict__ perm, int* __restrict__ work, int n) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    perm[k] = k;
-    work[k] = 0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= n; k += gridDim.x * blockDim.x) {
+    perm[k] = k < n ? k : 0;   // perm[n]: no tile with limiter work yet
+    if (k < n) work[k] = 0;
   }
 }
 
@@ -727,8 +744,10 @@ __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const i
   __shared__ Window W;
   __shared__ PPStage PS;
   if (*A.done) return;
-  if ((int)blockIdx.x >= *nseg) return;
-  const int4 it = seg[blockIdx.x];
+  const int n = *nseg;
+  if ((int)blockIdx.x >= n) return;
+  // the list is sorted by first row: each XCD takes a contiguous row band
+  const int4 it = seg[xcd_tile(blockIdx.x, n)];
   if (it.w <= 0) return;
   const P phys = make_phys<P>(A.phys);
   double amx = 0.0, amy = 0.0;
@@ -897,8 +916,40 @@ __global__ void __launch_bounds__(PART_CUT_T) part_cut_kernel(const float* __res
       }
       st[e] = x;
     }
-    seg[b0 + k] = make_int4(0, s * STRIP, st[0], st[1] - st[0]);
+    seg[budget + b0 + k] = make_int4(0, s * STRIP, st[0], st[1] - st[0]);
   }
+}
+
+// Row-major order of the list (first row, then strip), so that the list kernel's
+// XCD-aware order gives each XCD a band of rows across all strips: bitonic sort
+// of (first row, strip, index) keys in LDS, one block.
+__global__ void __launch_bounds__(PART_T) part_sort_kernel(int4* __restrict__ seg, const int* __restrict__ nseg,
+                                                          int budget) {
+  __shared__ unsigned long long key[PART_MAX_SEGMENTS];
+  const int t = threadIdx.x, n = *nseg;
+  int P = 1;
+  while (P < n) P <<= 1;
+  const int4* raw = seg + budget;
+  for (int i = t; i < P; i += PART_T)
+    key[i] = i < n ? ((unsigned long long)(unsigned)raw[i].z << 32) | ((unsigned long long)(raw[i].y / STRIP) << 12) |
+                         (unsigned long long)i
+                   : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < P; i += PART_T) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned long long a = key[i], b = key[ixj];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = t; i < n; i += PART_T) seg[i] = raw[key[i] & 0xFFFull];
 }
 
 __global__ void fill_kernel(float* __restrict__ p, float v, size_t n) {
@@ -936,10 +987,12 @@ __global__ void FAM_OE_ATTR oe2d_kernel(OEArgs A, Inst in, int H) {
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
+  const int T = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int i0 = (T % gridDim.x) * STRIP, j0 = (T / gridDim.x) * H;
   if (K == 6 && A.k6_table)
-    oe_tile<K, P, true>(phys, A, in, blockIdx.x * STRIP, blockIdx.y * H, H, W, bad);
+    oe_tile<K, P, true>(phys, A, in, i0, j0, H, W, bad);
   else
-    oe_tile<K, P, false>(phys, A, in, blockIdx.x * STRIP, blockIdx.y * H, H, W, bad);
+    oe_tile<K, P, false>(phys, A, in, i0, j0, H, W, bad);
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
 
@@ -1140,6 +1193,7 @@ void launch_partition(const float* row_cost, float* pref, void* state, int strip
   PartState* ps = static_cast<PartState*>(state);
   hipLaunchKernelGGL(part_scan_kernel, dim3(strips), dim3(PART_T), 0, s, row_cost, pref, ny, ps);
   hipLaunchKernelGGL(part_cut_kernel, dim3(strips), dim3(PART_CUT_T), 0, s, pref, strips, ny, budget, ps, seg, nseg);
+  hipLaunchKernelGGL(part_sort_kernel, dim3(1), dim3(PART_T), 0, s, seg, nseg, budget);
 }
 void launch_fill(float* p, float v, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<size_t>(1024, (n + 255) / 256)), dim3(256), 0, s, p, v, n);
