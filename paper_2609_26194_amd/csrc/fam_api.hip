@@ -362,12 +362,12 @@ static fam_status init_segments(fam_ctx* c) {
     return FAM_ERR_DEVICE;
   const int strips = (f.nx + fam::STRIP - 1) / fam::STRIP;
   c->seg_budget = 4 * cus;   // one stage wave per SIMD
-  if (strips > c->seg_budget || strips > fam::PART_MAX_STRIPS || c->seg_budget > fam::PART_MAX_SEGMENTS) {
+  if (strips > c->seg_budget || strips > fam::PART_MAX_STRIPS) {
     c->seg_budget = 0;
     return FAM_OK;
   }
   const size_t rows = (size_t)strips * f.ny;
-  if (hipMalloc(&c->seg, sizeof(int4) * 2 * c->seg_budget) != hipSuccess ||   // the list, then its cut order
+  if (hipMalloc(&c->seg, sizeof(int4) * c->seg_budget) != hipSuccess ||
       hipMalloc(&c->nseg, sizeof(int)) != hipSuccess || hipMalloc(&c->row_cost, sizeof(float) * rows) != hipSuccess ||
       hipMalloc(&c->row_pref, sizeof(float) * rows) != hipSuccess ||
       hipMalloc(&c->part_state, fam::partition_state_bytes()) != hipSuccess)

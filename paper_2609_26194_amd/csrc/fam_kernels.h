@@ -92,8 +92,6 @@ void launch_partition(const float* row_cost, float* pref, void* state, int strip
                       int* nseg, hipStream_t s);
 void launch_fill(float* p, float v, size_t n, hipStream_t s);
 constexpr int PART_MAX_STRIPS = 1024;
-constexpr int PART_MAX_SEGMENTS = 4096;   // list length the partition can sort
-// seg holds 2 * budget entries: the list (row-major) and, after it, the cut order
 // point values of the stage reconstruction at every cell's flux points (test export)
 void launch_dbg_recon(int dim, int k, int nc, const double* U, const Inst& in, double* vals, hipStream_t s);
 void launch_oe2d(int k, int sys, const OEArgs& A, const Inst& in, int H, hipStream_t s);

@@ -746,7 +746,7 @@ __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const i
   if (*A.done) return;
   const int n = *nseg;
   if ((int)blockIdx.x >= n) return;
-  // the list is sorted by first row: each XCD takes a contiguous row band
+  // the list is ordered by row band: each XCD takes a contiguous share
   const int4 it = seg[xcd_tile(blockIdx.x, n)];
   if (it.w <= 0) return;
   const P phys = make_phys<P>(A.phys);
@@ -835,8 +835,9 @@ __global__ void __launch_bounds__(PART_CUT_T) part_cut_kernel(const float* __res
                                                               int budget, const PartState* __restrict__ ps,
                                                               int4* __restrict__ seg, int* __restrict__ nseg) {
   __shared__ float sC[PART_MAX_STRIPS];
+  __shared__ int sn[PART_MAX_STRIPS];   // segments per strip
   __shared__ float sp[PART_LDS_ROWS];
-  __shared__ int s_n, s_base, s_all;
+  __shared__ int s_all;
   __shared__ float s_Cs;
   const int t = threadIdx.x, s = blockIdx.x, lane = t & 63;
   const float* __restrict__ P = pref + (size_t)s * ny;
@@ -873,34 +874,31 @@ __global__ void __launch_bounds__(PART_CUT_T) part_cut_kernel(const float* __res
       if (fits) hi = tau;
       else lo = tau;
     }
-    // this strip's count, the counts of the strips before it, and all
+    // every strip's count (<= budget at a bound that fits) and their sum
     const float inv = 1.0f / (hi - R);
-    int before = 0, all = 0, mine = 0;
+    int all = 0;
     for (int q = lane; q < strips; q += 64) {
-      const float x = sC[q] * inv;
-      const int n = max(1, (int)ceilf(x));   // <= budget at a bound that fits
+      const int n = max(1, (int)ceilf(sC[q] * inv));
+      sn[q] = n;
       all += n;
-      if (q < s) before += n;
-      if (q == s) mine = n;
     }
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-      all += __shfl_xor(all, m);
-      before += __shfl_xor(before, m);
-      mine += __shfl_xor(mine, m);
-    }
+    for (int m = 1; m < 64; m <<= 1) all += __shfl_xor(all, m);
     if (lane == 0) {
-      s_n = mine;
-      s_base = before;
       s_all = all;
       s_Cs = sC[s];
     }
   }
   __syncthreads();
-  const int n = s_n, b0 = s_base;
+  const int n = sn[s];
   const float Cs = s_Cs;
   if (s == 0 && t == 0) *nseg = s_all;
   for (int k = t; k < n; k += PART_CUT_T) {
+    // list position: segments ordered by their index within the strip, then by
+    // strip (the k-th segments of all strips cover similar rows, so each XCD's
+    // contiguous share of the list is a band of rows across the strips)
+    int pos = 0;
+    for (int q = 0; q < strips; ++q) pos += min(sn[q], k) + (q < s && sn[q] > k ? 1 : 0);
     int st[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -916,40 +914,8 @@ __global__ void __launch_bounds__(PART_CUT_T) part_cut_kernel(const float* __res
       }
       st[e] = x;
     }
-    seg[budget + b0 + k] = make_int4(0, s * STRIP, st[0], st[1] - st[0]);
+    seg[pos] = make_int4(0, s * STRIP, st[0], st[1] - st[0]);
   }
-}
-
-// Row-major order of the list (first row, then strip), so that the list kernel's
-// XCD-aware order gives each XCD a band of rows across all strips: bitonic sort
-// of (first row, strip, index) keys in LDS, one block.
-__global__ void __launch_bounds__(PART_T) part_sort_kernel(int4* __restrict__ seg, const int* __restrict__ nseg,
-                                                          int budget) {
-  __shared__ unsigned long long key[PART_MAX_SEGMENTS];
-  const int t = threadIdx.x, n = *nseg;
-  int P = 1;
-  while (P < n) P <<= 1;
-  const int4* raw = seg + budget;
-  for (int i = t; i < P; i += PART_T)
-    key[i] = i < n ? ((unsigned long long)(unsigned)raw[i].z << 32) | ((unsigned long long)(raw[i].y / STRIP) << 12) |
-                         (unsigned long long)i
-                   : ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = t; i < P; i += PART_T) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const unsigned long long a = key[i], b = key[ixj];
-          if ((a > b) == ((i & k) == 0)) {
-            key[i] = b;
-            key[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  for (int i = t; i < n; i += PART_T) seg[i] = raw[key[i] & 0xFFFull];
 }
 
 __global__ void fill_kernel(float* __restrict__ p, float v, size_t n) {
@@ -1193,7 +1159,6 @@ void launch_partition(const float* row_cost, float* pref, void* state, int strip
   PartState* ps = static_cast<PartState*>(state);
   hipLaunchKernelGGL(part_scan_kernel, dim3(strips), dim3(PART_T), 0, s, row_cost, pref, ny, ps);
   hipLaunchKernelGGL(part_cut_kernel, dim3(strips), dim3(PART_CUT_T), 0, s, pref, strips, ny, budget, ps, seg, nseg);
-  hipLaunchKernelGGL(part_sort_kernel, dim3(1), dim3(PART_T), 0, s, seg, nseg, budget);
 }
 void launch_fill(float* p, float v, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)std::min<size_t>(1024, (n + 255) / 256)), dim3(256), 0, s, p, v, n);
