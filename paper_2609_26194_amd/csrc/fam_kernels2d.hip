@@ -657,6 +657,23 @@ __device__ __forceinline__ void flush_wave_results(double amax_x, double amax_y,
   }
 }
 
+// Position in a heavy-first order (nh tiles with limiter work first, then the
+// others) that workgroup L of N takes: the heavy tiles in turn over the XCDs,
+// the others in the XCD-aware order (each XCD a contiguous range).  A bijection
+// of [0, N).
+__device__ __forceinline__ int heavy_first_slot(int L, int N, int nh) {
+  if (L < nh) return L;
+  const int x = L % NXCD;
+  int base = 0, first = 0;
+  for (int q = 0; q <= x; ++q) {
+    const int f = nh + ((q - nh) % NXCD + NXCD) % NXCD;   // first light position on XCD q
+    const int cnt = f < N ? (N - 1 - f) / NXCD + 1 : 0;
+    if (q < x) base += cnt;
+    else first = f;
+  }
+  return nh + base + (L - first) / NXCD;
+}
+
 template <int K, class P, bool PP>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
@@ -671,20 +688,8 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
     const int strips = (in.nx + STRIP - 1) / STRIP;
     // tiles with limiter work first (spread over the XCDs in turn), then the
     // others in the XCD-aware order of their row-major index
-    const int N = gridDim.x, L = blockIdx.x, nh = A.tile_perm[N];
-    int idx = L;
-    if (L >= nh) {
-      const int x = L % NXCD;
-      int base = 0, first = 0;
-      for (int q = 0; q <= x; ++q) {
-        const int f = nh + ((q - nh) % NXCD + NXCD) % NXCD;   // first light position on XCD q
-        const int cnt = f < N ? (N - 1 - f) / NXCD + 1 : 0;
-        if (q < x) base += cnt;
-        else first = f;
-      }
-      idx = nh + base + (L - first) / NXCD;
-    }
-    tile = A.tile_perm[idx];
+    const int N = gridDim.x;
+    tile = A.tile_perm[heavy_first_slot(blockIdx.x, N, A.tile_perm[N])];
     i0 = (tile % strips) * STRIP;
     j0 = (tile / strips) * H;
     PS.nwork = 0;
@@ -929,10 +934,14 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
   __shared__ PPStage PS;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
+  // one item per workgroup: the XCD-aware order (limiter on: heavy items first)
+  const bool one_each = (int)gridDim.x == nwork;
 #pragma unroll 1
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     // limiter on: items in the order of the previous launch's limiter work
-    const int wi = PP ? A.tile_perm[w] : w;
+    int wi;
+    if constexpr (PP) wi = A.tile_perm[one_each ? heavy_first_slot(w, nwork, A.tile_perm[nwork]) : w];
+    else wi = one_each ? xcd_tile(w, nwork) : w;
     const int4 it = work[wi];             // (instance, i0, j0, H)
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
@@ -968,9 +977,10 @@ __global__ void FAM_OE_ATTR oe2d_batched_kernel(OEArgs A, const Inst* __restrict
   __shared__ Window W;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
+  const bool one_each = (int)gridDim.x == nwork;   // then the XCD-aware order
 #pragma unroll 1
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-    const int4 it = work[w];
+    const int4 it = work[one_each ? xcd_tile(w, nwork) : w];
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
     if (K == 6 && A.k6_table)
