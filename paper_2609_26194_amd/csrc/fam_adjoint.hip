@@ -70,6 +70,13 @@ __device__ __forceinline__ size_t wrap_idx(const AdjMesh& m, int i, int j) {
   return (size_t)wrap1(j, m.ny) * m.nx + wrap1(i, m.nx);
 }
 
+// this block's tile of the grid in the XCD-aware order (neighbouring tiles,
+// which share halo cache lines, run under one L2)
+__device__ __forceinline__ int2 block_tile() {
+  const int T = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  return make_int2(T % gridDim.x, T / gridDim.x);
+}
+
 // periodic image of an index at most one period outside [0, n)
 __device__ __forceinline__ int wrap_near(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -289,7 +296,8 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
   __shared__ double tu[12][GTC];
   __shared__ double tl[12][GTC];
   const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
-  const int i0 = blockIdx.x * ADJ_TX, j0 = blockIdx.y * ADJ_TY;
+  const int2 bt = block_tile();
+  const int i0 = bt.x * ADJ_TX, j0 = bt.y * ADJ_TY;
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < m.nx && j < m.ny;
 #pragma unroll
@@ -411,7 +419,8 @@ __global__ void __launch_bounds__(ADJ_T) adj_gather_kernel(AdjMesh m, const doub
   constexpr int NCF = ncoef2d(K);
   __shared__ double sh[NCF][GTC];
   const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
-  const int i0 = blockIdx.x * ADJ_TX, j0 = blockIdx.y * ADJ_TY;
+  const int2 bt = block_tile();
+  const int i0 = bt.x * ADJ_TX, j0 = bt.y * ADJ_TY;
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < m.nx && j < m.ny;
   double acc[4][3];
@@ -423,6 +432,14 @@ __global__ void __launch_bounds__(ADJ_T) adj_gather_kernel(AdjMesh m, const doub
     const int py = p / GT, px = p - py * GT;
     src[t] = p < GTC ? wrap_idx(m, i0 - 1 + px, j0 - 1 + py) : 0;
   }
+  // component c + 1's tile is loaded into registers while component c is gathered
+  double nxt[NLP][NCF];
+#pragma unroll
+  for (int t = 0; t < NLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+#pragma unroll
+    for (int l = 0; l < NCF; ++l) nxt[t][l] = p < GTC ? abar[(size_t)l * m.plane + src[t]] : 0.0;
+  }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     __syncthreads();
@@ -431,10 +448,19 @@ __global__ void __launch_bounds__(ADJ_T) adj_gather_kernel(AdjMesh m, const doub
       const int p = threadIdx.x + t * ADJ_T;
       if (p < GTC) {
 #pragma unroll
-        for (int l = 0; l < NCF; ++l) sh[l][p] = abar[(size_t)(c * NCF + l) * m.plane + src[t]];
+        for (int l = 0; l < NCF; ++l) sh[l][p] = nxt[t][l];
       }
     }
     __syncthreads();
+    if (c < 3) {
+#pragma unroll
+      for (int t = 0; t < NLP; ++t) {
+        const int p = threadIdx.x + t * ADJ_T;
+#pragma unroll
+        for (int l = 0; l < NCF; ++l)
+          nxt[t][l] = p < GTC ? abar[(size_t)((c + 1) * NCF + l) * m.plane + src[t]] : 0.0;
+      }
+    }
     acc[c][0] = acc[c][1] = acc[c][2] = 0.0;
     if (inside) {
 #pragma unroll
@@ -598,8 +624,9 @@ constexpr int OES = 23;
 template <int K>
 __global__ void __launch_bounds__(ADJ_T) oe_adj_pre_kernel(AdjMesh m, const double* __restrict__ Un,
                                                            double* __restrict__ cs) {
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  const int2 bt = block_tile();
+  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
+  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
   const Patch P = patch_of(m, i, j);
   const size_t id = P.id(4);
@@ -631,8 +658,9 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
                                                          const double* __restrict__ cs,
                                                          const double* __restrict__ lam, double dt, double gk,
                                                          double* __restrict__ lamN, double* __restrict__ os) {
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  const int2 bt = block_tile();
+  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
+  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
   const Patch P = patch_of(m, i, j);
   const size_t id = P.id(4), il = P.id(3), ir = P.id(5), ib = P.id(1), it = P.id(7);
@@ -735,8 +763,9 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
 // face-centre value adjoints of every cell: [c][r, l, t, b]
 __global__ void __launch_bounds__(ADJ_T) oe_adj_b_kernel(AdjMesh m, const double* __restrict__ os,
                                                          double* __restrict__ cb) {
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  const int2 bt = block_tile();
+  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
+  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   if (i >= m.nx || j >= m.ny) return;
   const size_t id = (size_t)j * m.nx + i;
   const size_t il = (size_t)j * m.nx + wrap_near(i - 1, m.nx), ir = (size_t)j * m.nx + wrap_near(i + 1, m.nx);
@@ -770,7 +799,8 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_c_kernel(AdjMesh m, const double
                                                          const double* __restrict__ cb, double* __restrict__ lamN) {
   __shared__ double sh[OE_TILE_PLANES][GTC];
   const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
-  const int i0 = blockIdx.x * ADJ_TX, j0 = blockIdx.y * ADJ_TY;
+  const int2 bt = block_tile();
+  const int i0 = bt.x * ADJ_TX, j0 = bt.y * ADJ_TY;
   const int i = i0 + tx, j = j0 + ty;
   constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;
 #pragma unroll
@@ -846,8 +876,9 @@ __global__ void __launch_bounds__(ADJ_T) adj_seed_kernel(AdjMesh m, double x0, d
                                                          const double* __restrict__ U, double* __restrict__ lam,
                                                          double* __restrict__ partial) {
   __shared__ double red[ADJ_T / 64];
-  const int i = blockIdx.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = blockIdx.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+  const int2 bt = block_tile();
+  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
+  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
   double part = 0.0;
   if (i < m.nx && j < m.ny) {
     const size_t id = (size_t)j * m.nx + i;

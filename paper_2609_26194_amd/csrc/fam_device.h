@@ -16,6 +16,17 @@
 
 namespace fam {
 
+// XCD-aware tile order.  The hardware hands consecutive workgroups to the chip's
+// 8 XCDs in turn; tile xcd_tile(L, N) of workgroup L gives each XCD one
+// contiguous range of the N tiles (row-major: neighbouring tiles of the same
+// rows), so the cache lines that neighbouring tiles share stay in one L2.
+// A bijection of [0, N) for any N; only where tiles run changes.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int L, int N) {
+  const int x = L % NXCD, slot = L / NXCD, q = N / NXCD, r = N % NXCD;
+  return x * q + min(x, r) + slot;
+}
+
 // ---------------------------------------------------------------------------
 // 4-point Gauss-Legendre rule on [-1/2, 1/2] (nodes +-GS0, +-GS1; weights sum
 // to one).  Standard tabulated values of the rule on [-1, 1], halved.

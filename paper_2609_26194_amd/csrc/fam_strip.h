@@ -23,17 +23,6 @@ struct Window {
 // once every read of row r-1 in the current iteration is done
 __device__ __forceinline__ int slot_of(int r) { return ((r % 3) + 3) % 3; }
 
-// XCD-aware tile order.  The hardware hands consecutive workgroups to the chip's
-// 8 XCDs in turn; tile xcd_tile(L, N) of workgroup L gives each XCD one
-// contiguous range of the N tiles (row-major: neighbouring strips of the same
-// rows), so the cache lines that neighbouring strips share stay in one L2.
-// A bijection of [0, N) for any N; only where tiles run changes.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_tile(int L, int N) {
-  const int x = L % NXCD, slot = L / NXCD, q = N / NXCD, r = N % NXCD;
-  return x * q + min(x, r) + slot;
-}
-
 template <int NPLU>
 __device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0, int r,
                                           int lane, double (&reg)[NPLU]) {
