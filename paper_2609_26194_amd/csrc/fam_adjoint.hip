@@ -49,6 +49,12 @@ constexpr int ADJ_TX = 16, ADJ_TY = 16, ADJ_T = ADJ_TX * ADJ_TY;
 constexpr int GT = ADJ_TX + 2;
 constexpr int GTC = GT * GT;
 constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;   // tile positions per thread (at most two)
+// the coefficient-adjoint kernel: one wave per block (8 x 8 cells), so that the
+// four blocks a CU holds (its registers allow one wave per SIMD) load and compute
+// independently
+constexpr int CTX = 8, CTY = 8, CT = CTX * CTY;
+constexpr int CGX = CTX + 2, CGC = CGX * (CTY + 2);
+constexpr int CNLP = (CGC + CT - 1) / CT;
 
 struct AdjMesh {
   int nx, ny;
@@ -214,7 +220,8 @@ __device__ __forceinline__ void face_adj(bool xface, const double (&muL)[3], con
   }
 }
 
-__device__ __forceinline__ void tile_mu(const double (&tl)[12][GTC], int pos, double (&mu)[4][3]) {
+template <int TC>
+__device__ __forceinline__ void tile_mu(const double (&tl)[12][TC], int pos, double (&mu)[4][3]) {
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -285,26 +292,25 @@ __device__ __forceinline__ void coef_group(double g, const double (&cf)[4][ncoef
 }
 
 template <int K>
-__global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double* __restrict__ U,
-                                                         const double* __restrict__ lam, double scale,
-                                                         const double* __restrict__ alpha,
-                                                         double* __restrict__ abar, double* __restrict__ partial) {
+__global__ void __launch_bounds__(CT) adj_coef_kernel(AdjMesh m, const double* __restrict__ U,
+                                                      const double* __restrict__ lam, double scale,
+                                                      const double* __restrict__ alpha,
+                                                      double* __restrict__ abar, double* __restrict__ partial) {
   constexpr int NC = 4, NCF = ncoef2d(K);
-  __shared__ double red[ADJ_T / 64];
-  // the 12 planes of U and of scale * lam over the block's cells and a one-cell
-  // ring (the kernel's registers allow one block per CU, so the tiles fit)
-  __shared__ double tu[12][GTC];
-  __shared__ double tl[12][GTC];
-  const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
+  __shared__ double red[CT / 64];
+  // the 12 planes of U and of scale * lam over the block's cells and a one-cell ring
+  __shared__ double tu[12][CGC];
+  __shared__ double tl[12][CGC];
+  const int tx = threadIdx.x % CTX, ty = threadIdx.x / CTX;
   const int2 bt = block_tile();
-  const int i0 = bt.x * ADJ_TX, j0 = bt.y * ADJ_TY;
+  const int i0 = bt.x * CTX, j0 = bt.y * CTY;
   const int i = i0 + tx, j = j0 + ty;
   const bool inside = i < m.nx && j < m.ny;
 #pragma unroll
-  for (int t = 0; t < NLP; ++t) {
-    const int p = threadIdx.x + t * ADJ_T;
-    if (p < GTC) {
-      const int py = p / GT, px = p - py * GT;
+  for (int t = 0; t < CNLP; ++t) {
+    const int p = threadIdx.x + t * CT;
+    if (p < CGC) {
+      const int py = p / CGX, px = p - py * CGX;
       const size_t src = wrap_idx(m, i0 - 1 + px, j0 - 1 + py);
 #pragma unroll
       for (int q = 0; q < 12; ++q) {
@@ -319,7 +325,7 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
     const double g = m.gamma;
     const double ax = alpha[0], ay = alpha[1];
     const double idx_ = 1.0 / m.dx, idy = 1.0 / m.dy;
-    const int base = (ty + 1) * GT + (tx + 1);   // this cell in the tiles
+    const int base = (ty + 1) * CGX + (tx + 1);   // this cell in the tiles
     double cf[NC][NCF];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -328,7 +334,7 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
       for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int l = b * 3 + a, pos = base + (b - 1) * GT + (a - 1);
+          const int l = b * 3 + a, pos = base + (b - 1) * CGX + (a - 1);
           const bool x_used = (K >= 5) ? (l != 1 && l != 7) : (l == 4);
           const bool y_used = (K >= 5) ? (l != 3 && l != 5) : (l == 4);
           u0[l] = tu[c * 3 + 0][pos];
@@ -367,10 +373,10 @@ __global__ void __launch_bounds__(ADJ_T) adj_coef_kernel(AdjMesh m, const double
     // y-faces: side 0 = top face (this cell below), side 1 = bottom face
     {
       double nb[NC][3];
-      tile_mu(tl, base + GT, nb);
+      tile_mu(tl, base + CGX, nb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_adj(false, mu[c], nb[c], idy, B[0][c], T[0][c]);
-      tile_mu(tl, base - GT, nb);
+      tile_mu(tl, base - CGX, nb);
 #pragma unroll
       for (int c = 0; c < NC; ++c) face_adj(false, nb[c], mu[c], idy, B[1][c], T[1][c]);
     }
@@ -964,7 +970,8 @@ static fam_status adj_alloc(fam_ctx* c, int ncp, int seg) {
   s->seg = seg;
   const size_t L = c->len * sizeof(double), D = sizeof(double);
   const int nx = c->cfg[0].nx, ny = c->cfg[0].ny;
-  const size_t nb = (size_t)((nx + fam::ADJ_TX - 1) / fam::ADJ_TX) * ((ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
+  // per-block partials: the coefficient kernel's 8 x 8 blocks outnumber the 16 x 16 ones
+  const size_t nb = (size_t)((nx + fam::CTX - 1) / fam::CTX) * ((ny + fam::CTY - 1) / fam::CTY);
   struct A {
     void** p;
     size_t bytes;
@@ -989,12 +996,13 @@ static void rT_apply(fam_ctx* c, const fam::AdjMesh& m, const double* Us, const 
                      double dt, double* out, int accumulate, double* out2, double b2, int acc2, hipStream_t st) {
   FamAdjointScratch* s = c->adj;
   const dim3 grid((m.nx + fam::ADJ_TX - 1) / fam::ADJ_TX, (m.ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
-  const int nb = grid.x * grid.y;
   // wave speeds of Us and their first argmax
   hipLaunchKernelGGL(fam::adj_alpha_part_kernel, dim3(fam::ALPHA_BLOCKS), dim3(256), 0, st, m, Us, s->apv, s->api);
   hipLaunchKernelGGL(fam::adj_alpha_final_kernel, dim3(1), dim3(fam::RED_T), 0, st, s->apv, s->api,
                      fam::ALPHA_BLOCKS, s->smax, s->sidx);
-  hipLaunchKernelGGL((fam::adj_coef_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Us, lam_out, b * dt, s->smax,
+  const dim3 cgrid((m.nx + fam::CTX - 1) / fam::CTX, (m.ny + fam::CTY - 1) / fam::CTY);
+  const int nb = cgrid.x * cgrid.y;   // blocks of the coefficient kernel: its alpha partials
+  hipLaunchKernelGGL((fam::adj_coef_kernel<K>), cgrid, dim3(fam::CT), 0, st, m, Us, lam_out, b * dt, s->smax,
                      s->abar, s->partial);
   hipLaunchKernelGGL((fam::adj_gather_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, s->abar, lam_out, b, out,
                      accumulate, out2, b2, acc2);
