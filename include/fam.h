@@ -82,6 +82,11 @@ typedef struct {
                              limiter toward the cell average that keeps density
                              and pressure >= min(1e-13, rho_avg, p_avg) at all 32
                              flux points of every cell).  0 = off.               */
+  int dt_rule;            /* time step without dt_fixed (Sec. 4): 0 = C dx/alpha_x
+                             (2D: C/(alpha_x/dx + alpha_y/dy)), the rule of the
+                             discontinuous problems; 1 = the same with dx^{k/3},
+                             dy^{k/3} in place of dx, dy, the rule of the smooth
+                             accuracy tests.                                      */
 } fam_config;
 
 typedef struct fam_ctx fam_ctx;

@@ -57,6 +57,7 @@ class Config:
     cfl: float = 0.2
     k6_jump_from_table: bool = False
     pp: bool = False               # positivity limiter on the stage reconstruction (Euler)
+    dt_rule: int = 0               # 0: C dx / alpha; 1: C dx^{k/3} / alpha (smooth tests, Sec. 4)
     phys: object = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -335,13 +336,16 @@ def residual(U, cfg):
 # time step and SSP-RK3
 # ----------------------------------------------------------------------------
 def cfl_dt(U, cfg):
-    """Discontinuous-problem time step of Sec. 4 from the cell averages."""
+    """Time step of Sec. 4 from the cell averages: C dx / alpha for the discontinuous
+    problems, or C dx^{k/3} / alpha for the smooth accuracy tests (dt_rule = 1); in 2D
+    C / (alpha_x / hx + alpha_y / hy) with hx, hy those lengths."""
     avg = U[:, 0]
     ax = max_speed(cfg.phys, avg, 0)
+    e = cfg.k / 3.0 if cfg.dt_rule == 1 else 1.0
     if cfg.dim == 1:
-        return float(cfg.cfl * cfg.dx / ax)
+        return float(cfg.cfl * cfg.dx ** e / ax)
     ay = max_speed(cfg.phys, avg, 1)
-    return float(cfg.cfl / (ax / cfg.dx + ay / cfg.dy))
+    return float(cfg.cfl / (ax / cfg.dx ** e + ay / cfg.dy ** e))
 
 
 def rk3_stage(s, U0, Us, dt, cfg):

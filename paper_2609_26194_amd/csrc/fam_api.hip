@@ -60,6 +60,7 @@ static fam_status validate(const fam_config& c) {
   if (c.system == FAM_EULER && !(c.gamma > 1.0)) return FAM_ERR_ARG;
   if ((size_t)c.nx * (size_t)(c.dim == 2 ? c.ny : 1) > ((size_t)1 << 31)) return FAM_ERR_ARG;
   if (c.pp && !(c.system == FAM_EULER && c.dim == 2)) return FAM_ERR_ARG;
+  if (c.dt_rule != 0 && c.dt_rule != 1) return FAM_ERR_ARG;
   return FAM_OK;
 }
 
@@ -130,8 +131,9 @@ static fam_status init_steps(fam_ctx* c) {
     std::memset(&s, 0, sizeof(s));
     const fam_config& f = c->cfg[i];
     s.cfl = f.cfl;
-    s.dx = (f.x1 - f.x0) / f.nx;
-    s.dy = c->dim == 2 ? (f.y1 - f.y0) / f.ny : 1.0;
+    const double e = f.dt_rule == 1 ? f.k / 3.0 : 1.0;
+    s.hx = std::pow((f.x1 - f.x0) / f.nx, e);
+    s.hy = c->dim == 2 ? std::pow((f.y1 - f.y0) / f.ny, e) : 1.0;
     s.dim = c->dim;
   }
   HIP_TRY(hipMemcpy(c->st, h.data(), sizeof(StepState) * c->ninst, hipMemcpyHostToDevice));

@@ -69,7 +69,7 @@ struct StepState {
   double t_final;          // <= 0: none
   double dt_fixed;         // > 0: use instead of the CFL rule
   double cfl;
-  double dx, dy;
+  double hx, hy;           // lengths of the time-step rule: dx, dy or dx^{k/3}, dy^{k/3}
   int dim;
   int done;
   int steps;

@@ -244,7 +244,7 @@ __global__ void step_begin_kernel(StepState* st, int ninst, int parity, double d
     dt = dt_fixed;
   } else {
     const double ax = s.alpha[q][0][0], ay = s.alpha[q][0][1];
-    dt = (s.dim == 1) ? s.cfl * s.dx / ax : s.cfl / (ax / s.dx + ay / s.dy);
+    dt = (s.dim == 1) ? s.cfl * s.hx / ax : s.cfl / (ax / s.hx + ay / s.hy);
   }
   double tn = s.t + dt;
   if (t_final > 0.0) {
