@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--adjoint-n", type=int, default=1024)
     p.add_argument("--adjoint-steps", type=int, default=400)
     p.add_argument("--adjoint-checkpoint", type=int, default=20)
+    p.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
+    p.add_argument("--dmr-t", type=float, default=0.2)
     p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     return p.parse_args()
 
@@ -331,6 +333,57 @@ def k6_leg(n, steps, warmup):
             "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}}
 
 
+def dmr_leg(t_final, nx=1440, ny=480):
+    """The paper's double Mach reflection run: [0, 3] x [0, 1], 1440 x 480, FAM5, OE Type II,
+    positivity limiter, CFL 0.2, to t_final; cell-updates/s and the split of one step's time
+    between the three RK stage launches and the OE launch (HIP events on the library stream,
+    at the final state)."""
+    import torch
+    import fam_inputs as fi
+    from paper_2609_26194_amd import Fam, FamConfig
+    from paper_2609_26194_amd.fam import fam_oe, fam_stage
+    cfg = FamConfig(dim=2, nx=nx, ny=ny, x0=0.0, x1=3.0, y0=0.0, y1=1.0, k=5, system="euler", oe="type2",
+                    cfl=0.2, pp=True, dmr=True)
+    U0 = torch.tensor(fi.double_mach(nx, ny), dtype=torch.float64).cuda()
+    fam = Fam(cfg)
+    tuned = fam.autotune(U0)
+    U = U0.clone()
+    fam.run(U, 0.0, 5)   # warm-up
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, t = fam.run(U, t_final, 10 ** 7)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fam.check()
+    # one step's launches at the final state
+    dtd = fam.dt(U)
+    W1, W2, W3 = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
+    calls = [("stage", lambda: fam_stage(fam.h, 0, U, U, W1, dtd)), ("stage", lambda: fam_stage(fam.h, 1, U, W1, W2, dtd)),
+             ("stage", lambda: fam_stage(fam.h, 2, U, W2, W3, dtd)), ("oe", lambda: fam_oe(fam.h, W3, W1, dtd))]
+    tot = {"stage": 0.0, "oe": 0.0}
+    reps = 10
+    for rep in range(reps + 1):
+        for name, fn in calls:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fam.stream.wait_stream(torch.cuda.current_stream())
+            e0.record(fam.stream)
+            fn()
+            e1.record(fam.stream)
+            e1.synchronize()
+            if rep:
+                tot[name] += e0.elapsed_time(e1) / reps
+    fam.close()
+    return {"workload": f"double Mach reflection {nx}x{ny} on [0,3]x[0,1], FAM5, OE Type II, positivity limiter, "
+                        f"CFL 0.2, to t = {t:.4f}", "steps": steps, "cell_updates_per_s": nx * ny * steps / elapsed,
+            "ms_per_step": elapsed / steps * 1e3, "seconds": elapsed,
+            # standalone launches of one step (each stage launch re-cuts its segment list; inside the
+            # graph-replayed step that happens once), and the OE's share of them
+            "launch_ms": {"rk_stages": tot["stage"], "oe": tot["oe"]},
+            "oe_fraction": tot["oe"] / (tot["stage"] + tot["oe"]),
+            "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}}
+
+
 def main_workload(args, n, k):
     """The headline measurement: cell-updates/s of the full step and the stage-kernel roofline."""
     import torch
@@ -385,8 +438,8 @@ def main():
         ingest_counters(*args.ingest_counters)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of this build",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the library runs a mesh or a batch on a "
+              f"single GPU", file=sys.stderr)
         sys.exit(2)
     n, k = args.n, args.k
     out = {}
@@ -398,6 +451,9 @@ def main():
     if not args.no_batched:
         log("batched workload")
         out["batched"] = batched(args.batched_steps)
+    if not args.no_dmr:
+        log("double Mach reflection")
+        out["dmr"] = dmr_leg(args.dmr_t)
     if not args.no_adjoint:
         log("adjoint workload")
         out["adjoint"] = adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_checkpoint)

@@ -322,3 +322,18 @@ def smooth_density_wave_direction(n, rng, ny=None):
         drho = sum(b[m] * np.sin(2.0 * math.pi * (ks[m][0] * X + ks[m][1] * Y) + phi[m]) for m in range(4))
         return np.stack([drho, 0.5 * drho, 0.5 * drho, 0.25 * drho])
     return moments_2d(f, 0.0, 1.0, 0.0, 1.0, n, ny)
+
+
+def double_mach(nx, ny, gamma=1.4, x1=3.0, y1=1.0):
+    """Double Mach reflection initial data on [0, x1] x [0, y1] (Sec. 4 example): the state
+    (rho, u, v, p) = (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5) behind the incident shock
+    x = 1/6 + y / sqrt(3) (to its left) and (1.4, 0, 0, 1) ahead of it; moments by Gauss
+    quadrature of the piecewise-constant data."""
+    prim = ((8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5), (1.4, 0.0, 0.0, 1.0))
+    cons = [euler_conservative(np.array(r), np.array(u), np.array(p), np.array(v), gamma) for r, u, v, p in prim]
+
+    def f(X, Y):
+        behind = X < 1.0 / 6.0 + Y / math.sqrt(3.0)
+        return np.stack([np.where(behind, float(cons[0][c]), float(cons[1][c])) for c in range(4)])
+
+    return moments_2d(f, 0.0, x1, 0.0, y1, nx, ny)

@@ -87,6 +87,15 @@ typedef struct {
                              discontinuous problems; 1 = the same with dx^{k/3},
                              dy^{k/3} in place of dx, dy, the rule of the smooth
                              accuracy tests.                                      */
+  int dmr;                /* 2D Euler only: the boundaries of the double Mach
+                             reflection example (Sec. 4): post-shock inflow on the
+                             left, outflow (copy) on the right, on the bottom the
+                             post-shock state for x < 1/6 and a reflecting wall
+                             beyond, on the top the exact moving shock (post-shock
+                             state for cell centres x < 1/6 + (y1 + 20 t)/sqrt 3,
+                             pre-shock state beyond); states (rho, u, v, p) =
+                             (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5) and
+                             (1.4, 0, 0, 1).  bc_x, bc_y are ignored.  0 = off.  */
 } fam_config;
 
 typedef struct fam_ctx fam_ctx;
@@ -174,7 +183,7 @@ fam_status fam_set_tiling(fam_ctx* ctx, int stage_H, int oe_H);
  * |x|' = sign(x) with sign(0) = 0, maxima pass the derivative to their first
  * maximal entry, the zero-denominator branch of the OE coefficient has zero
  * derivative.  Synchronous.  Supported contexts: one 2D Euler instance,
- * periodic in x and y, OE off or Type II, no positivity limiter, k = 6 with the
+ * periodic in x and y (no dmr boundaries), OE off or Type II, no positivity limiter, k = 6 with the
  * jumps of p_6; any other context returns FAM_ERR_STATE.  FAM_ERR_ARG for NULL
  * pointers, nsteps < 1, dt <= 0 or checkpoint_every < 1; FAM_ERR_NOMEM when the
  * checkpoints (ceil(nsteps / checkpoint_every) states) and the segment tape
@@ -184,7 +193,8 @@ fam_status fam_set_tiling(fam_ctx* ctx, int stage_H, int oe_H);
 fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
                        int checkpoint_every, const double* dJdUT, double* dJdU0, double* J_out);
 
-/* Test-only exports (single-instance contexts; FAM_ERR_STATE otherwise; FAM_ERR_ARG
+/* Test-only exports (single-instance contexts; FAM_ERR_STATE otherwise, and for
+ * fam_dbg_recon also with the dmr boundaries; FAM_ERR_ARG
  * for NULL pointers).  Asynchronous.
  *
  * fam_dbg_recon: point values of the stage reconstruction p_k of U (Sec. 2.4;

@@ -25,6 +25,8 @@ moment of the nearest interior cell (Remark after Algorithm 1).
 """
 from dataclasses import dataclass, field
 
+import math
+
 import torch
 
 from . import exact
@@ -58,6 +60,7 @@ class Config:
     k6_jump_from_table: bool = False
     pp: bool = False               # positivity limiter on the stage reconstruction (Euler)
     dt_rule: int = 0               # 0: C dx / alpha; 1: C dx^{k/3} / alpha (smooth tests, Sec. 4)
+    dmr: bool = False              # double Mach reflection boundaries (Sec. 4 example)
     phys: object = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -101,13 +104,66 @@ def _ghost_index(n, g, bc):
     raise ValueError(f"unknown boundary condition {bc!r}")
 
 
-def pad(U, cfg, g=2):
-    """Return U with g ghost layers on every side (layout preserved)."""
+def pad(U, cfg, g=2, t=0.0):
+    """Return U with g ghost layers on every side (layout preserved); t is the time of
+    time-dependent boundary data (the double Mach reflection's upper boundary)."""
+    if cfg.dmr:
+        return _pad_dmr(U, cfg, g, t)
     ix = _ghost_index(cfg.nx, g, cfg.bc_x)
     if cfg.dim == 1:
         return U[..., ix]
     iy = _ghost_index(cfg.ny, g, cfg.bc_y)
     return U[..., iy, :][..., ix]
+
+
+def dmr_states(gamma):
+    """Conservative states behind and ahead of the incident Mach 10 shock of the double
+    Mach reflection example (Sec. 4): (rho, u, v, p) = (8, 8.25 cos 30deg, -8.25 sin 30deg,
+    116.5) and (1.4, 0, 0, 1)."""
+    out = []
+    for rho, u, v, p in ((8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5),
+                         (1.4, 0.0, 0.0, 1.0)):
+        out.append([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+    return out
+
+
+def _pad_dmr(U, cfg, g, t):
+    """Ghost cells of the double Mach reflection example, cell by cell:
+    * above the mesh, the exact moving shock: post-shock state where the cell centre
+      lies left of x = 1/6 + (y1 + 20 t) / sqrt(3), pre-shock state beyond;
+    * below the mesh, the post-shock state where the cell centre has x < 1/6, else a
+      reflecting wall: the mirror image of the interior row, with the average and
+      x-moment of rho v and the y-moments of rho, rho u, E negated;
+    * left of the mesh, the post-shock state; right of it, a copy of the last column.
+    Constant states have zero first moments."""
+    post, pre = dmr_states(cfg.gamma)
+    C, M, ny, nx = U.shape
+    out = torch.empty((C, M, ny + 2 * g, nx + 2 * g), dtype=U.dtype)
+    xs = 1.0 / 6.0 + (cfg.y1 + 20.0 * t) / math.sqrt(3.0)
+    const = lambda q: torch.tensor([[q[c], 0.0, 0.0][m] for c in range(C) for m in range(M)],
+                                   dtype=U.dtype).reshape(C, M)
+    Qpost, Qpre = const(post), const(pre)
+    for jj in range(ny + 2 * g):
+        r = jj - g
+        for ii in range(nx + 2 * g):
+            ci = ii - g
+            xc = cfg.x0 + (ci + 0.5) * cfg.dx
+            if r >= ny:
+                out[:, :, jj, ii] = Qpost if xc < xs else Qpre
+                continue
+            if (r < 0 and xc < 1.0 / 6.0) or (r >= 0 and ci < 0):
+                out[:, :, jj, ii] = Qpost
+                continue
+            gi = min(ci, nx - 1)
+            if r < 0:
+                v = U[:, :, -1 - r, gi].clone()
+                v[2, 0] = -v[2, 0]
+                v[2, 1] = -v[2, 1]
+                v[0, 2], v[1, 2], v[3, 2] = -v[0, 2], -v[1, 2], -v[3, 2]
+                out[:, :, jj, ii] = v
+            else:
+                out[:, :, jj, ii] = U[:, :, r, gi]
+    return out
 
 
 # ----------------------------------------------------------------------------
@@ -256,7 +312,7 @@ def pp_apply(vals, avg, theta1, theta2):
 # ----------------------------------------------------------------------------
 # semi-discrete operator R(U)
 # ----------------------------------------------------------------------------
-def residual_1d(U, cfg):
+def residual_1d(U, cfg, t=0.0):
     """R(U) of eq. (1dSemi) for every cell: returns [C, 2, n]."""
     phys = cfg.phys
     nodes, weights = gauss4()
@@ -291,11 +347,11 @@ def points_2d():
     return pts
 
 
-def residual_2d(U, cfg):
+def residual_2d(U, cfg, t=0.0):
     """R(U) of eq. (11) on the Cartesian mesh: returns [C, 3, ny, nx]."""
     phys = cfg.phys
     nodes, weights = gauss4()
-    Upad = pad(U, cfg)
+    Upad = pad(U, cfg, t=t)
     monos, coef = reconstruct(Upad, cfg)                   # [C, P, ny+2, nx+2]
     vals = point_values(monos, coef, points_2d())          # [C, 32, ny+2, nx+2]
     if cfg.pp:
@@ -328,8 +384,8 @@ def residual_2d(U, cfg):
     return torch.stack([R0, R1, R2], dim=1)
 
 
-def residual(U, cfg):
-    return residual_1d(U, cfg) if cfg.dim == 1 else residual_2d(U, cfg)
+def residual(U, cfg, t=0.0):
+    return residual_1d(U, cfg) if cfg.dim == 1 else residual_2d(U, cfg, t)
 
 
 # ----------------------------------------------------------------------------
@@ -348,9 +404,12 @@ def cfl_dt(U, cfg):
     return float(cfg.cfl / (ax / cfg.dx ** e + ay / cfg.dy ** e))
 
 
-def rk3_stage(s, U0, Us, dt, cfg):
-    """Stage s (0, 1, 2) of the Shu-Osher form of SSP-RK3 (eq. 12)."""
-    Ls = Us + dt * residual(Us, cfg)
+STAGE_TIME = (0.0, 1.0, 0.5)   # stage s evaluates R at t_n + STAGE_TIME[s] dt
+
+
+def rk3_stage(s, U0, Us, dt, cfg, t=0.0):
+    """Stage s (0, 1, 2) of the Shu-Osher form of SSP-RK3 (eq. 12); t = t_n (boundary data)."""
+    Ls = Us + dt * residual(Us, cfg, t + STAGE_TIME[s] * dt)
     if s == 0:
         return Ls
     if s == 1:
@@ -358,10 +417,10 @@ def rk3_stage(s, U0, Us, dt, cfg):
     return U0 / 3.0 + (2.0 / 3.0) * Ls
 
 
-def rk3(U0, dt, cfg):
-    U1 = rk3_stage(0, U0, U0, dt, cfg)
-    U2 = rk3_stage(1, U0, U1, dt, cfg)
-    return rk3_stage(2, U0, U2, dt, cfg)
+def rk3(U0, dt, cfg, t=0.0):
+    U1 = rk3_stage(0, U0, U0, dt, cfg, t)
+    U2 = rk3_stage(1, U0, U1, dt, cfg, t)
+    return rk3_stage(2, U0, U2, dt, cfg, t)
 
 
 # ----------------------------------------------------------------------------
@@ -429,18 +488,18 @@ def oe_delta_1d(Un, dt, cfg):
     return torch.exp(-beta * dt * sig / cfg.dx)
 
 
-def oe_2d(Un, dt, cfg):
-    """OE pass of eq. (2dOE_system) with the common factor delta_{i,j}."""
+def oe_2d(Un, dt, cfg, t=0.0):
+    """OE pass of eq. (2dOE_system) with the common factor delta_{i,j}; t: time of Un."""
     if cfg.oe == "off":
         return Un
-    delta = oe_delta_2d(Un, dt, cfg)
+    delta = oe_delta_2d(Un, dt, cfg, t)
     return torch.stack([Un[:, 0], Un[:, 1] * delta, Un[:, 2] * delta], dim=1)
 
 
-def oe_delta_2d(Un, dt, cfg):
+def oe_delta_2d(Un, dt, cfg, t=0.0):
     """Damping factor delta_{i,j} of every cell in the OE pass of eq. (2dOE_system)."""
     phys = cfg.phys
-    Upad = pad(Un, cfg)
+    Upad = pad(Un, cfg, t=t)
     monos, coef = _jump_monos_coef(Upad, cfg)                # [C, P, ny+2, nx+2]
     cx = coef[:, :, 1:-1, :]
     r = point_values(monos, cx, [(0.5, 0.0)])[:, 0]
@@ -465,23 +524,24 @@ def oe_delta_2d(Un, dt, cfg):
     return torch.exp(-bx * dt * sx / cfg.dx - by * dt * sy / cfg.dy)
 
 
-def oe(Un, dt, cfg):
-    return oe_1d(Un, dt, cfg) if cfg.dim == 1 else oe_2d(Un, dt, cfg)
+def oe(Un, dt, cfg, t=0.0):
+    return oe_1d(Un, dt, cfg) if cfg.dim == 1 else oe_2d(Un, dt, cfg, t)
 
 
-def oe_delta(Un, dt, cfg):
-    return oe_delta_1d(Un, dt, cfg) if cfg.dim == 1 else oe_delta_2d(Un, dt, cfg)
+def oe_delta(Un, dt, cfg, t=0.0):
+    return oe_delta_1d(Un, dt, cfg) if cfg.dim == 1 else oe_delta_2d(Un, dt, cfg, t)
 
 
 # ----------------------------------------------------------------------------
 # driver
 # ----------------------------------------------------------------------------
-def step(U, cfg, dt=None):
-    """One FAM step; dt=None computes the CFL time step from U. Returns (U_new, dt)."""
+def step(U, cfg, dt=None, t=0.0):
+    """One FAM step from time t; dt=None computes the CFL time step from U.
+    Returns (U_new, dt)."""
     if dt is None:
         dt = cfl_dt(U, cfg)
-    Un = rk3(U, dt, cfg)
-    return oe(Un, dt, cfg), dt
+    Un = rk3(U, dt, cfg, t)
+    return oe(Un, dt, cfg, t + dt), dt
 
 
 def run(U, cfg, nsteps=None, t_final=None, dt=None):
@@ -496,7 +556,7 @@ def run(U, cfg, nsteps=None, t_final=None, dt=None):
         h = dt if dt is not None else cfl_dt(U, cfg)
         if t_final is not None and t + h > t_final:
             h = t_final - t
-        U, _ = step(U, cfg, h)
+        U, _ = step(U, cfg, h, t)
         t += h
         steps += 1
     return U, t, steps

@@ -61,6 +61,7 @@ static fam_status validate(const fam_config& c) {
   if ((size_t)c.nx * (size_t)(c.dim == 2 ? c.ny : 1) > ((size_t)1 << 31)) return FAM_ERR_ARG;
   if (c.pp && !(c.system == FAM_EULER && c.dim == 2)) return FAM_ERR_ARG;
   if (c.dt_rule != 0 && c.dt_rule != 1) return FAM_ERR_ARG;
+  if (c.dmr && !(c.system == FAM_EULER && c.dim == 2)) return FAM_ERR_ARG;
   return FAM_OK;
 }
 
@@ -81,6 +82,24 @@ static Inst make_inst(const fam_ctx* c, int i) {
   in.dy = c->dim == 2 ? (f.y1 - f.y0) / f.ny : 1.0;
   in.bcx = f.bc_x;
   in.bcy = f.bc_y;
+  if (f.dmr) {
+    in.dmr = 1;
+    in.bcx = in.bcy = FAM_BC_TRANSMISSIVE;
+    in.x0 = f.x0;
+    in.ytop = f.y1;
+    // (rho, u, v, p) behind and ahead of the shock -> (rho, rho u, rho v, E)
+    const double pi = 3.14159265358979323846;
+    const double prim[2][4] = {{8.0, 8.25 * std::cos(pi / 6.0), -8.25 * std::sin(pi / 6.0), 116.5},
+                               {1.4, 0.0, 0.0, 1.0}};
+    double* out[2] = {in.qpost, in.qpre};
+    for (int q = 0; q < 2; ++q) {
+      const double* w = prim[q];
+      out[q][0] = w[0];
+      out[q][1] = w[0] * w[1];
+      out[q][2] = w[0] * w[2];
+      out[q][3] = w[3] / (f.gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2]);
+    }
+  }
   return in;
 }
 
@@ -96,6 +115,8 @@ Inst inst_for(const fam_ctx* c, int i, int parity, int stage) {
   }
   in.dt = &s->dt;
   in.done = &s->done;
+  in.t_end = &s->t;
+  in.t_ofs = stage == 0 ? 1.0 : stage == 2 ? 0.5 : 0.0;   // stage times t_n, t_n + dt, t_n + dt/2; OE t_n + dt
   return in;
 }
 
@@ -533,7 +554,7 @@ extern "C" fam_status fam_set_tiling(fam_ctx* c, int stage_H, int oe_H) {
 
 extern "C" fam_status fam_dbg_recon(fam_ctx* c, const double* U, double* vals) {
   if (!c || !U || !vals) return FAM_ERR_ARG;
-  if (c->ninst != 1) return FAM_ERR_STATE;
+  if (c->ninst != 1 || c->cfg[0].dmr) return FAM_ERR_STATE;
   const Inst in = inst_for(c, 0, 0, 0);
   fam::launch_dbg_recon(c->dim, c->k, c->nc, U, in, vals, c->stream);
   return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;

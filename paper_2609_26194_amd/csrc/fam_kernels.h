@@ -27,6 +27,14 @@ struct Inst {
   double* alpha_out;       // [2] max-accumulators for the stage output state
   const double* dt;        // time step of the current step
   const int* done;         // instance finished (fam_run), may be null
+  // double Mach reflection boundaries (dmr != 0): the boundary time of a launch is
+  // *t_end - t_ofs * dt (t_end: the step's end time; t_ofs 1, 0, 1/2 for the RK
+  // stages, 0 for OE); x0, ytop: domain; qpost, qpre: conservative states
+  int dmr;
+  const double* t_end;
+  double t_ofs;
+  double x0, ytop;
+  double qpost[4], qpre[4];
 };
 
 struct StageArgs {

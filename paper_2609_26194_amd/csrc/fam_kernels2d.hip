@@ -259,6 +259,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   const double i2dx = 0.5 * idx_, i2dy = 0.5 * idy;
   const double ax = in.alpha_in[0], ay = in.alpha_in[1];
   const double dt = *in.dt;
+  const double tb = in.dmr ? *in.t_end - in.t_ofs * dt : 0.0;   // boundary time of this stage
   const bool use_u0 = A.ca != 0.0;
   const double* __restrict__ Us = A.Us + in.offset;
   const double* __restrict__ U0 = A.U0 + in.offset;
@@ -267,7 +268,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
-    fetch_row<NPLU>(Us, in, i0, r, lane, reg);
+    fetch_row<NPLU>(Us, in, i0, r, lane, reg, tb);
     store_row<NPLU>(W, slot_of(r), lane, reg);
   }
   __syncthreads();
@@ -289,7 +290,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       if (A.row_cost) t_row = clock64();
     }
     const bool pre = (r + 2 <= rend + 1);
-    if (pre) fetch_row<NPLU>(Us, in, i0, r + 2, lane, reg);
+    if (pre) fetch_row<NPLU>(Us, in, i0, r + 2, lane, reg, tb);
     const bool fin = (r - 1 >= j0) && out_lane;   // this iteration finishes row r-1
     double u0row[NPLU];
     if (fin && use_u0) {
@@ -500,6 +501,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   const int rend = min(j0 + H, in.ny);
   const bool out_lane = lane >= 2 && lane <= LANES - 3 && i < in.nx;
   const double dt = *in.dt;
+  const double tb = in.dmr ? *in.t_end : 0.0;   // OE: the end of the step
   const double cx = dt / in.dx, cy = dt / in.dy;
   const double* __restrict__ Un = A.Un + in.offset;
   double* __restrict__ Uo = A.Uout + in.offset;
@@ -507,7 +509,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
-    fetch_row<NPLU>(Un, in, i0, r, lane, reg);
+    fetch_row<NPLU>(Un, in, i0, r, lane, reg, tb);
     store_row<NPLU>(W, slot_of(r), lane, reg);
   }
   __syncthreads();
@@ -534,7 +536,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
 #pragma unroll 1
   for (int r = j0 - 1; r <= rend; ++r) {
     const bool pre = (r + 2 <= rend + 1);
-    if (pre) fetch_row<NPLU>(Un, in, i0, r + 2, lane, reg);
+    if (pre) fetch_row<NPLU>(Un, in, i0, r + 2, lane, reg, tb);
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1);
 

@@ -23,11 +23,46 @@ struct Window {
 // once every read of row r-1 in the current iteration is done
 __device__ __forceinline__ int slot_of(int r) { return ((r % 3) + 3) % 3; }
 
+// the double Mach reflection ghost cells of row r, column ci (at least one
+// outside the mesh) at boundary time tb; see fam_config.dmr
+template <int NPLU>
+__device__ __forceinline__ void dmr_ghost(const double* __restrict__ U, const Inst& in, int r, int ci, double tb,
+                                          double (&reg)[NPLU]) {
+  const double xc = in.x0 + (ci + 0.5) * in.dx;
+  const double* q = nullptr;
+  if (r >= in.ny)   // top: the exact shock line at the upper boundary
+    q = xc < 1.0 / 6.0 + (in.ytop + 20.0 * tb) * 0.57735026918962576451 ? in.qpost : in.qpre;
+  else if (r < 0 ? xc < 1.0 / 6.0 : ci < 0)   // bottom inflow part, left inflow
+    q = in.qpost;
+  if (q) {
+#pragma unroll
+    for (int p = 0; p < NPLU; ++p) reg[p] = p % 3 == 0 ? q[p / 3] : 0.0;
+    return;
+  }
+  // right outflow (copy of the last column) and, below the mesh, the reflecting
+  // wall: mirror image of row -1 - r with rho v and the y-moments of the other
+  // components negated
+  const int gi = ci >= in.nx ? in.nx - 1 : ci;
+  const int gj = r < 0 ? -1 - r : r;
+  const size_t base = (size_t)gj * in.nx + gi;
+#pragma unroll
+  for (int p = 0; p < NPLU; ++p) {
+    const double v = U[p * in.plane + base];
+    const bool neg = r < 0 && ((p / 3 == 2) ? (p % 3 != 2) : (p % 3 == 2));
+    reg[p] = neg ? -v : v;
+  }
+}
+
 template <int NPLU>
 __device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0, int r,
-                                          int lane, double (&reg)[NPLU]) {
+                                          int lane, double (&reg)[NPLU], double tb) {
+  const int ci = i0 - 2 + lane;
+  if (in.dmr && (r < 0 || r >= in.ny || ci < 0 || ci >= in.nx)) {
+    dmr_ghost<NPLU>(U, in, r, ci, tb, reg);
+    return;
+  }
   const int gj = ghost(r, in.ny, in.bcy);
-  const int gi = ghost(i0 - 2 + lane, in.nx, in.bcx);
+  const int gi = ghost(ci, in.nx, in.bcx);
   const size_t base = (size_t)gj * in.nx + gi;
 #pragma unroll
   for (int p = 0; p < NPLU; ++p) reg[p] = U[p * in.plane + base];
