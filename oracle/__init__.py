@@ -26,6 +26,10 @@ two-dimensional OE jumps use p_6 by default).  The optional positivity limiter
 (``Config.pp``) is this project's design of the standard safeguard the paper
 cites without stating it; it is pinned by invariants (identity on admissible
 data, admissible and average-preserving output, tightness of the scaling).
+The double Mach reflection boundary data (``Config.dmr``; time-dependent
+ghost cells at each RK stage's time) follow the example's statement in Sec. 4
+with cell-centre assignment at the shock; parity unpinned beyond the scheme's
+invariants (the paper prints only a figure for this example).
 """
 from .physics import NonPhysicalState, gauss4  # noqa: F401
 from .scheme import Config, cfl_dt, oe, residual, rk3, rk3_stage, run, step  # noqa: F401
