@@ -1039,7 +1039,7 @@ __global__ void __launch_bounds__(256) type1_pass1_kernel(const double* __restri
     if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = s;
   }
   __syncthreads();
-  if (threadIdx.x < nc) {
+  if ((int)threadIdx.x < nc) {
     const int c = threadIdx.x;
     partial[blockIdx.x * 4 + c] = ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
   }
@@ -1049,7 +1049,7 @@ __global__ void __launch_bounds__(256) type1_pass1_kernel(const double* __restri
 __global__ void type1_mean_kernel(const double* __restrict__ partial, int nblocks, Inst in, int nc,
                                   double* __restrict__ stats, double* __restrict__ dmax) {
   if (threadIdx.x < 8) dmax[threadIdx.x] = 0.0;
-  if (threadIdx.x < nc) {
+  if ((int)threadIdx.x < nc) {
     const int c = threadIdx.x;
     double s = 0.0;
     for (int b = 0; b < nblocks; ++b) s += partial[b * 4 + c];
@@ -1082,7 +1082,7 @@ __global__ void __launch_bounds__(256) type1_pass3_kernel(const double* __restri
 
 __global__ void type1_final_kernel(const double* __restrict__ dmax, Inst in, int nc,
                                    double* __restrict__ stats) {
-  if (threadIdx.x < nc) {
+  if ((int)threadIdx.x < nc) {
     const int c = threadIdx.x;
     stats[in.id * 8 + c] = dmax[c];
     stats[in.id * 8 + 4 + c] = 1e-14 * fmax(dmax[4 + c], 1.0);

@@ -9,7 +9,6 @@ time.  Coarse meshes of the example's domain [0, 3] x [0, 1] run a few steps
 (the top shock moves by about a cell) with the positivity limiter, as in the
 paper's run.
 """
-import numpy as np
 import pytest
 import torch
 

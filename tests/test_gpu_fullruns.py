@@ -14,7 +14,6 @@ import os
 
 import numpy as np
 import pytest
-import torch
 
 import fam_inputs as fi
 from gpu_util import both_configs, log, needs_gpu, to_dev

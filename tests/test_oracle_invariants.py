@@ -11,7 +11,6 @@
 * The positivity limiter leaves admissible reconstructions untouched and makes
   every flux point admissible.
 """
-import math
 
 import numpy as np
 import pytest
