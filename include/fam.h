@@ -106,7 +106,8 @@ fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx** out);
 /* A context advancing n_inst independent 2D instances together (one launch per
  * RK stage and one OE launch for all of them).  All instances share dim = 2,
  * k, system, gamma, oe, cfl and the boundary conditions; sizes and domains may
- * differ.  Every instance uses its own time step. */
+ * differ.  Every instance uses its own time step.  FAM_ERR_ARG for OE Type I
+ * or the dmr boundaries (single contexts only). */
 fam_status fam_init_batched(const fam_config* per_instance, int n_inst, void* hip_stream,
                             fam_ctx** out);
 

@@ -87,18 +87,7 @@ static Inst make_inst(const fam_ctx* c, int i) {
     in.bcx = in.bcy = FAM_BC_TRANSMISSIVE;
     in.x0 = f.x0;
     in.ytop = f.y1;
-    // (rho, u, v, p) behind and ahead of the shock -> (rho, rho u, rho v, E)
-    const double pi = 3.14159265358979323846;
-    const double prim[2][4] = {{8.0, 8.25 * std::cos(pi / 6.0), -8.25 * std::sin(pi / 6.0), 116.5},
-                               {1.4, 0.0, 0.0, 1.0}};
-    double* out[2] = {in.qpost, in.qpre};
-    for (int q = 0; q < 2; ++q) {
-      const double* w = prim[q];
-      out[q][0] = w[0];
-      out[q][1] = w[0] * w[1];
-      out[q][2] = w[0] * w[2];
-      out[q][3] = w[3] / (f.gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2]);
-    }
+    in.dmr_einv = 1.0 / (f.gamma - 1.0);
   }
   return in;
 }
@@ -322,6 +311,7 @@ extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_s
       return FAM_ERR_ARG;
   }
   if (per[0].oe == FAM_OE_TYPE1) return FAM_ERR_ARG;   // global statistics per instance: single contexts only
+  if (per[0].dmr) return FAM_ERR_ARG;   // the double Mach reflection boundaries: single contexts only
   fam_ctx* c = new (std::nothrow) fam_ctx();
   if (!c) return FAM_ERR_NOMEM;
   c->cfg.assign(per, per + n);

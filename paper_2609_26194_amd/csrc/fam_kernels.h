@@ -29,12 +29,11 @@ struct Inst {
   const int* done;         // instance finished (fam_run), may be null
   // double Mach reflection boundaries (dmr != 0): the boundary time of a launch is
   // *t_end - t_ofs * dt (t_end: the step's end time; t_ofs 1, 0, 1/2 for the RK
-  // stages, 0 for OE); x0, ytop: domain; qpost, qpre: conservative states
+  // stages, 0 for OE); x0, ytop: domain; dmr_einv = 1 / (gamma - 1)
   int dmr;
   const double* t_end;
   double t_ofs;
-  double x0, ytop;
-  double qpost[4], qpre[4];
+  double x0, ytop, dmr_einv;
 };
 
 struct StageArgs {

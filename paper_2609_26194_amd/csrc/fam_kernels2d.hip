@@ -28,6 +28,7 @@
 // patch; sigma = max over components; delta = exp(-beta^x dt sigma^x/dx -
 // beta^y dt sigma^y/dy); first moments scaled by delta, averages copied.
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "fam_device.h"
@@ -243,7 +244,7 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
 // ---------------------------------------------------------------------------
 // stage tile
 // ---------------------------------------------------------------------------
-template <int K, class P, bool PP>
+template <int K, class P, bool PP, bool DMR = false>
 __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, int i0, int j0, int H,
                            Window& W, PPStage& PS, double& amax_x, double& amax_y, bool& bad) {
   constexpr int NC = P::NC;
@@ -259,7 +260,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   const double i2dx = 0.5 * idx_, i2dy = 0.5 * idy;
   const double ax = in.alpha_in[0], ay = in.alpha_in[1];
   const double dt = *in.dt;
-  const double tb = in.dmr ? *in.t_end - in.t_ofs * dt : 0.0;   // boundary time of this stage
+  const double tb = DMR ? *in.t_end - in.t_ofs * dt : 0.0;   // boundary time of this stage
   const bool use_u0 = A.ca != 0.0;
   const double* __restrict__ Us = A.Us + in.offset;
   const double* __restrict__ U0 = A.U0 + in.offset;
@@ -268,7 +269,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
-    fetch_row<NPLU>(Us, in, i0, r, lane, reg, tb);
+    fetch_row<NPLU, DMR>(Us, in, i0, r, lane, reg, tb);
     store_row<NPLU>(W, slot_of(r), lane, reg);
   }
   __syncthreads();
@@ -290,7 +291,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       if (A.row_cost) t_row = clock64();
     }
     const bool pre = (r + 2 <= rend + 1);
-    if (pre) fetch_row<NPLU>(Us, in, i0, r + 2, lane, reg, tb);
+    if (pre) fetch_row<NPLU, DMR>(Us, in, i0, r + 2, lane, reg, tb);
     const bool fin = (r - 1 >= j0) && out_lane;   // this iteration finishes row r-1
     double u0row[NPLU];
     if (fin && use_u0) {
@@ -490,7 +491,7 @@ __device__ __forceinline__ void centre_values(const Window& W, int c, int col, i
   out[3] = centre_dot<K, FULL, 3>(u, Seq{});
 }
 
-template <int K, class P, bool FULL>
+template <int K, class P, bool FULL, bool DMR = false>
 __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, int j0, int H,
                         Window& W, bool& bad) {
   constexpr int NC = P::NC;
@@ -501,7 +502,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   const int rend = min(j0 + H, in.ny);
   const bool out_lane = lane >= 2 && lane <= LANES - 3 && i < in.nx;
   const double dt = *in.dt;
-  const double tb = in.dmr ? *in.t_end : 0.0;   // OE: the end of the step
+  const double tb = DMR ? *in.t_end : 0.0;   // OE: the end of the step
   const double cx = dt / in.dx, cy = dt / in.dy;
   const double* __restrict__ Un = A.Un + in.offset;
   double* __restrict__ Uo = A.Uout + in.offset;
@@ -509,7 +510,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
-    fetch_row<NPLU>(Un, in, i0, r, lane, reg, tb);
+    fetch_row<NPLU, DMR>(Un, in, i0, r, lane, reg, tb);
     store_row<NPLU>(W, slot_of(r), lane, reg);
   }
   __syncthreads();
@@ -536,7 +537,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
 #pragma unroll 1
   for (int r = j0 - 1; r <= rend; ++r) {
     const bool pre = (r + 2 <= rend + 1);
-    if (pre) fetch_row<NPLU>(Un, in, i0, r + 2, lane, reg, tb);
+    if (pre) fetch_row<NPLU, DMR>(Un, in, i0, r + 2, lane, reg, tb);
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1);
 
@@ -676,7 +677,7 @@ __device__ __forceinline__ int heavy_first_slot(int L, int N, int nh) {
   return nh + base + (L - first) / NXCD;
 }
 
-template <int K, class P, bool PP>
+template <int K, class P, bool PP, bool DMR>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
   __shared__ PPStage PS;
@@ -700,7 +701,7 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
     i0 = (T % gridDim.x) * STRIP;
     j0 = (T / gridDim.x) * H;
   }
-  stage_tile<K, P, PP>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
+  stage_tile<K, P, PP, DMR>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
   if constexpr (PP) {
     if (threadIdx.x == 0) A.tile_work[tile] = PS.nwork;
@@ -745,7 +746,7 @@ __global__ void tile_identity_kernel(int* __restrict__ perm, int* __restrict__ w
   }
 }
 
-template <int K, class P>
+template <int K, class P, bool DMR>
 __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const int4* __restrict__ seg,
                                                     const int* __restrict__ nseg) {
   __shared__ Window W;
@@ -760,7 +761,7 @@ __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const i
   double amx = 0.0, amy = 0.0;
   bool bad = false;
   PS.nwork = 0;
-  stage_tile<K, P, true>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
+  stage_tile<K, P, true, DMR>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
 }
 
@@ -958,7 +959,7 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
 
-template <int K, class P>
+template <int K, class P, bool DMR>
 __global__ void FAM_OE_ATTR oe2d_kernel(OEArgs A, Inst in, int H) {
   __shared__ Window W;
   if (*A.done) return;
@@ -967,9 +968,9 @@ __global__ void FAM_OE_ATTR oe2d_kernel(OEArgs A, Inst in, int H) {
   const int T = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int i0 = (T % gridDim.x) * STRIP, j0 = (T / gridDim.x) * H;
   if (K == 6 && A.k6_table)
-    oe_tile<K, P, true>(phys, A, in, i0, j0, H, W, bad);
+    oe_tile<K, P, true, DMR>(phys, A, in, i0, j0, H, W, bad);
   else
-    oe_tile<K, P, false>(phys, A, in, i0, j0, H, W, bad);
+    oe_tile<K, P, false, DMR>(phys, A, in, i0, j0, H, W, bad);
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
 
@@ -1092,25 +1093,47 @@ __global__ void type1_final_kernel(const double* __restrict__ dmax, Inst in, int
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int K, class P>
-static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
+// the double Mach reflection boundaries are an Euler 2D option; other systems
+// compile only the plain instantiation
+template <class P>
+static bool dmr_of(const Inst& in) {
+  if constexpr (std::is_same_v<P, Euler<2>>)
+    return in.dmr != 0;
+  else
+    return false;
+}
+template <int K, class P, bool DMR>
+static void launch_stage2d_d(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
   if (A.pp) {
     const int ntiles = grid.x * grid.y;
-    hipLaunchKernelGGL((stage2d_kernel<K, P, true>), dim3(ntiles), dim3(LANES), 0, s, A, in, H);
+    hipLaunchKernelGGL((stage2d_kernel<K, P, true, DMR>), dim3(ntiles), dim3(LANES), 0, s, A, in, H);
     // up to one tile per wave slot of the chip every tile starts at once: the
     // order stays the identity set with the tile height
     if (ntiles > ORDER_MIN_TILES)
       hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, A.tile_work, const_cast<int*>(A.tile_perm),
                          ntiles);
   } else {
-    hipLaunchKernelGGL((stage2d_kernel<K, P, false>), grid, dim3(LANES), 0, s, A, in, H);
+    hipLaunchKernelGGL((stage2d_kernel<K, P, false, DMR>), grid, dim3(LANES), 0, s, A, in, H);
   }
+}
+template <int K, class P>
+static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
+  if constexpr (std::is_same_v<P, Euler<2>>) {
+    if (dmr_of<P>(in)) return launch_stage2d_d<K, P, true>(A, in, H, s);
+  }
+  launch_stage2d_d<K, P, false>(A, in, H, s);
 }
 template <int K, class P>
 static void launch_oe2d_t(const OEArgs& A, const Inst& in, int H, hipStream_t s) {
   dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
-  hipLaunchKernelGGL((oe2d_kernel<K, P>), grid, dim3(LANES), 0, s, A, in, H);
+  if constexpr (std::is_same_v<P, Euler<2>>) {
+    if (dmr_of<P>(in)) {
+      hipLaunchKernelGGL((oe2d_kernel<K, P, true>), grid, dim3(LANES), 0, s, A, in, H);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((oe2d_kernel<K, P, false>), grid, dim3(LANES), 0, s, A, in, H);
 }
 template <int K, class P>
 static void launch_stage2d_b(const StageArgs& A, const Inst* insts, const int4* work, int nwork, int nblocks,
@@ -1152,7 +1175,13 @@ void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, h
 template <int K, class P>
 static void launch_stage2d_list_t(const StageArgs& A, const Inst& in, const int4* seg, const int* nseg, int budget,
                                   hipStream_t s) {
-  hipLaunchKernelGGL((stage2d_list_kernel<K, P>), dim3(budget), dim3(LANES), 0, s, A, in, seg, nseg);
+  if constexpr (std::is_same_v<P, Euler<2>>) {
+    if (dmr_of<P>(in)) {
+      hipLaunchKernelGGL((stage2d_list_kernel<K, P, true>), dim3(budget), dim3(LANES), 0, s, A, in, seg, nseg);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((stage2d_list_kernel<K, P, false>), dim3(budget), dim3(LANES), 0, s, A, in, seg, nseg);
 }
 void launch_stage2d_list(int k, int sys, const StageArgs& A, const Inst& in, const int4* seg, const int* nseg,
                          int budget, hipStream_t s) {

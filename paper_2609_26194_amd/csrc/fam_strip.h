@@ -29,14 +29,19 @@ template <int NPLU>
 __device__ __forceinline__ void dmr_ghost(const double* __restrict__ U, const Inst& in, int r, int ci, double tb,
                                           double (&reg)[NPLU]) {
   const double xc = in.x0 + (ci + 0.5) * in.dx;
-  const double* q = nullptr;
+  int which = -1;   // 0: post-shock state, 1: pre-shock state, -1: copy or mirror
   if (r >= in.ny)   // top: the exact shock line at the upper boundary
-    q = xc < 1.0 / 6.0 + (in.ytop + 20.0 * tb) * 0.57735026918962576451 ? in.qpost : in.qpre;
+    which = xc < 1.0 / 6.0 + (in.ytop + 20.0 * tb) * 0.57735026918962576451 ? 0 : 1;
   else if (r < 0 ? xc < 1.0 / 6.0 : ci < 0)   // bottom inflow part, left inflow
-    q = in.qpost;
-  if (q) {
+    which = 0;
+  if (which >= 0) {
+    // (rho, u, v, p) = (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5) behind the shock,
+    // (1.4, 0, 0, 1) ahead; conservative, with 1/(gamma - 1) = in.dmr_einv
+    constexpr double rl = 8.0, ul = 8.25 * 0.86602540378443864676, vl = -8.25 * 0.5, pl = 116.5;
+    const double post[4] = {rl, rl * ul, rl * vl, pl * in.dmr_einv + 0.5 * rl * (ul * ul + vl * vl)};
+    const double pre[4] = {1.4, 0.0, 0.0, in.dmr_einv};
 #pragma unroll
-    for (int p = 0; p < NPLU; ++p) reg[p] = p % 3 == 0 ? q[p / 3] : 0.0;
+    for (int p = 0; p < NPLU; ++p) reg[p] = p % 3 == 0 ? (which == 0 ? post[p / 3] : pre[p / 3]) : 0.0;
     return;
   }
   // right outflow (copy of the last column) and, below the mesh, the reflecting
@@ -53,13 +58,17 @@ __device__ __forceinline__ void dmr_ghost(const double* __restrict__ U, const In
   }
 }
 
-template <int NPLU>
+// DMR: the instance uses the double Mach reflection boundaries (a separate
+// instantiation, so the plain kernels carry none of its registers)
+template <int NPLU, bool DMR>
 __device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0, int r,
                                           int lane, double (&reg)[NPLU], double tb) {
   const int ci = i0 - 2 + lane;
-  if (in.dmr && (r < 0 || r >= in.ny || ci < 0 || ci >= in.nx)) {
-    dmr_ghost<NPLU>(U, in, r, ci, tb, reg);
-    return;
+  if constexpr (DMR) {
+    if (r < 0 || r >= in.ny || ci < 0 || ci >= in.nx) {
+      dmr_ghost<NPLU>(U, in, r, ci, tb, reg);
+      return;
+    }
   }
   const int gj = ghost(r, in.ny, in.bcy);
   const int gi = ghost(ci, in.nx, in.bcx);
