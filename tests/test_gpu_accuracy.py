@@ -9,7 +9,15 @@ paper, and FAM3/FAM4 differ more than FAM5/FAM6).  The 2D table, which takes
 the CPU oracle minutes, is pinned here at N = 20 and 40.  One run per system is
 also compared with the oracle step for step (the whole time-step sequence,
 including the dx^{k/3} rule and the clipped last step).
+
+The appendix tables of first-moment errors (supp:1dBurMoment, supp:1dEulerMoment)
+are reproduced at every printed mesh size: the mean absolute error of the scaled
+first moment of the density (Burgers: u) within per-order factors of the printed
+value, and the observed order over the whole range of at least k - 0.5.
 """
+
+# the factor within which the first-moment errors reproduce the printed ones
+MOM_TOL = {3: 1.5, 4: 2.0, 5: 1.5, 6: 1.5}
 import math
 
 import numpy as np
@@ -109,3 +117,31 @@ def test_smooth_rule_runs_match_the_oracle(system, dim):
     err = rel_linf(U, ref)
     log(f"  rel Linf {err:.3e}")
     assert err <= 1e-12
+
+
+def _moment_table(table, k, ns, make, exact, T):
+    errs = []
+    for n in ns:
+        _, cfg = both_configs(dim=1, nx=n, x0=0.0, x1=2.0, k=k, system="burgers" if table == "burgers_mom" else "euler",
+                              oe="type2", cfl=0.1, dt_rule=1)
+        U, steps = _run(cfg, make(n), T)
+        e = float(np.abs(U[0, 1] - exact(n, T)[0, 1]).mean())
+        g = _gold(table, n, k)
+        log(f"  {table} FAM{k} N={n}: {steps} steps, first-moment error {e:.3e} (printed {g:.3e}, ratio {e / g:.3f})")
+        assert g / MOM_TOL[k] < e < g * MOM_TOL[k]
+        errs.append(e)
+    order = math.log(errs[0] / errs[-1]) / math.log(ns[-1] / ns[0])
+    log(f"  order {ns[0]} -> {ns[-1]}: {order:.2f}")
+    assert order > k - 0.5
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_burgers_moment_table(k):
+    _moment_table("burgers_mom", k, (30, 60, 90, 120, 150, 180), fi.burgers_smooth, fi.burgers_exact_moments,
+                  0.5 / math.pi)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_euler_1d_moment_table(k):
+    _moment_table("euler1d_mom", k, (20, 30, 40, 50, 60, 70), fi.smooth_euler_1d, fi.smooth_euler_1d_exact_density,
+                  2.0)
