@@ -30,6 +30,12 @@ The double Mach reflection boundary data (``Config.dmr``; time-dependent
 ghost cells at each RK stage's time) follow the example's statement in Sec. 4
 with cell-centre assignment at the shock; parity unpinned beyond the scheme's
 invariants (the paper prints only a figure for this example).
+The local characteristic-variable stage reconstruction (``Config.char_vars``,
+the FAM5 alternative timed in Sec. 4.3) transforms each cell's stencil with the
+textbook left eigenvectors of the x-direction flux Jacobian at the cell's own
+average and maps the coefficients back with the right eigenvectors (a reading:
+the paper names neither the direction nor the averaging state); pinned by the
+eigen-decomposition of the Jacobian and by Sec. 2.3's commutation remark.
 """
 from .physics import NonPhysicalState, gauss4  # noqa: F401
 from .scheme import Config, cfl_dt, oe, residual, rk3, rk3_stage, run, step  # noqa: F401

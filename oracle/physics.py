@@ -114,6 +114,54 @@ class Euler(Physics):
         rho = u[0]
         return torch.abs(u[1 + d] / rho) + torch.sqrt(self.gamma * p / rho)
 
+    def eigen(self, u, d=0):
+        """Left and right eigenvectors of the flux Jacobian in direction d at the states u.
+
+        Textbook forms (the paper uses them for the local characteristic-variable
+        FAM5 variant it times in Sec. 4.3 without printing them).  With c the sound
+        speed, H = (E + p)/rho the enthalpy, q^2 = |velocity|^2, b1 = (gamma - 1)/c^2
+        and b2 = b1 q^2 / 2, the eigenvalues are ordered (u_n - c, u_n, u_n + c) and,
+        in 2D, the shear wave u_n last.  Returns (L, R), each [C, C, ...], with
+        L = R^{-1} and the columns of R the right eigenvectors.
+        """
+        g = self.gamma
+        C = self.ncomp
+        rho = u[0]
+        vel = [u[1 + j] / rho for j in range(self.dim)]
+        p = self.pressure(u)
+        c = torch.sqrt(g * p / rho)
+        H = (u[-1] + p) / rho
+        q2 = sum(v * v for v in vel)
+        b1 = (g - 1.0) / (c * c)
+        b2 = 0.5 * b1 * q2
+        un = vel[d]
+        zero, one = torch.zeros_like(rho), torch.ones_like(rho)
+        R = [[zero] * C for _ in range(C)]
+        L = [[zero] * C for _ in range(C)]
+        # right eigenvectors (columns): acoustic -, entropy, acoustic +
+        for col, s in ((0, -1.0), (1, 0.0), (2, 1.0)):
+            R[0][col] = one
+            for j in range(self.dim):
+                R[1 + j][col] = vel[j] + (s * c if j == d else zero)
+            R[C - 1][col] = H + s * un * c if s != 0.0 else 0.5 * q2
+        # left eigenvectors (rows)
+        for row, s in ((0, 1.0), (2, -1.0)):
+            L[row][0] = 0.5 * (b2 + s * un / c)
+            for j in range(self.dim):
+                L[row][1 + j] = -0.5 * (b1 * vel[j] + (s / c if j == d else zero))
+            L[row][C - 1] = 0.5 * b1
+        L[1][0] = 1.0 - b2
+        for j in range(self.dim):
+            L[1][1 + j] = b1 * vel[j]
+        L[1][C - 1] = -b1
+        if self.dim == 2:
+            t = 1 - d                      # tangential direction: shear wave
+            R[1 + t][3] = one
+            R[3][3] = vel[t]
+            L[3][0] = -vel[t]
+            L[3][1 + t] = one
+        return (torch.stack([torch.stack(r) for r in L]), torch.stack([torch.stack(r) for r in R]))
+
 
 def rusanov(phys, ul, ur, d, alpha):
     """Lax-Friedrichs (Rusanov) flux 1/2 (f(ul) + f(ur)) - 1/2 alpha (ur - ul)."""

@@ -61,12 +61,15 @@ class Config:
     pp: bool = False               # positivity limiter on the stage reconstruction (Euler)
     dt_rule: int = 0               # 0: C dx / alpha; 1: C dx^{k/3} / alpha (smooth tests, Sec. 4)
     dmr: bool = False              # double Mach reflection boundaries (Sec. 4 example)
+    char_vars: bool = False        # stage reconstruction in local characteristic variables (Euler)
     phys: object = field(default=None, repr=False)
 
     def __post_init__(self):
         if self.dim == 1:
             self.ny = 1
         self.phys = make_physics(self.system, self.dim, self.gamma, self.a)
+        if self.char_vars and self.system != "euler":
+            raise ValueError("characteristic variables need the Euler equations")
 
     @property
     def dx(self):
@@ -232,6 +235,30 @@ def reconstruct(Upad, cfg, full_aux=False):
     return monos, coef
 
 
+def reconstruct_stage(Upad, cfg):
+    """The RK-stage reconstruction: componentwise in conservative variables, or with
+    cfg.char_vars in the local characteristic variables of each cell.
+
+    The characteristic variant (the FAM5 alternative timed in Sec. 4.3, Table
+    runtime-main Panel B): every cell maps its whole stencil of moments to the
+    characteristic variables of its own cell average with the left eigenvectors
+    of the x-direction flux Jacobian there, reconstructs each characteristic
+    field with the same linear operator, and maps the polynomial's coefficients
+    back with the right eigenvectors.  Sec. 2.3 notes that a linear reconstruction
+    commutes with a fixed change of variables, so both give the same polynomial
+    up to rounding; the variant only changes the cost.
+    """
+    if not cfg.char_vars:
+        return reconstruct(Upad, cfg)
+    monos, Rm = recon_matrix(cfg.dim, cfg.k)
+    S = stencil_1d(Upad, cfg.k) if cfg.dim == 1 else stencil_2d(Upad, cfg.k)
+    avg = Upad[:, 0, 1:-1] if cfg.dim == 1 else Upad[:, 0, 1:-1, 1:-1]   # the stencils' own cells
+    L, R = cfg.phys.eigen(avg, 0)
+    W = torch.einsum("ab...,bi...->ai...", L, S)           # characteristic stencil values
+    coef_w = torch.einsum("pi,ai...->ap...", Rm, W)        # reconstruct each field
+    return monos, torch.einsum("ca...,ap...->cp...", R, coef_w)
+
+
 def point_values(monos, coef, points):
     E = eval_matrix(monos, points)
     return torch.einsum("qp,cp...->cq...", E, coef)
@@ -317,7 +344,7 @@ def residual_1d(U, cfg, t=0.0):
     phys = cfg.phys
     nodes, weights = gauss4()
     Upad = pad(U, cfg)
-    monos, coef = reconstruct(Upad, cfg)                  # cells -1..n
+    monos, coef = reconstruct_stage(Upad, cfg)            # cells -1..n
     pts = [(0.5,), (-0.5,)] + [(x,) for x in nodes]
     vals = point_values(monos, coef, pts)                  # [C, 6, n+2]
     if cfg.pp:
@@ -352,7 +379,7 @@ def residual_2d(U, cfg, t=0.0):
     phys = cfg.phys
     nodes, weights = gauss4()
     Upad = pad(U, cfg, t=t)
-    monos, coef = reconstruct(Upad, cfg)                   # [C, P, ny+2, nx+2]
+    monos, coef = reconstruct_stage(Upad, cfg)             # [C, P, ny+2, nx+2]
     vals = point_values(monos, coef, points_2d())          # [C, 32, ny+2, nx+2]
     if cfg.pp:
         avg = Upad[:, 0, 1:-1, 1:-1]
