@@ -66,6 +66,7 @@ def parse():
     p.add_argument("--adjoint-checkpoint", type=int, default=20)
     p.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
     p.add_argument("--dmr-t", type=float, default=0.2)
+    p.add_argument("--no-char", action="store_true", help="skip the characteristic-variable comparison")
     p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     return p.parse_args()
 
@@ -333,6 +334,77 @@ def k6_leg(n, steps, warmup):
             "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}}
 
 
+def launch_split(fam, U, reps=10):
+    """Standalone launches of one step at the state U: the three RK stage launches and
+    the OE launch, each bracketed by HIP events on the library stream (ms, averaged)."""
+    import torch
+    from paper_2609_26194_amd.fam import fam_oe, fam_stage
+    dtd = fam.dt(U)
+    W1, W2, W3 = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
+    calls = [("stage", lambda: fam_stage(fam.h, 0, U, U, W1, dtd)), ("stage", lambda: fam_stage(fam.h, 1, U, W1, W2, dtd)),
+             ("stage", lambda: fam_stage(fam.h, 2, U, W2, W3, dtd)), ("oe", lambda: fam_oe(fam.h, W3, W1, dtd))]
+    tot = {"stage": 0.0, "oe": 0.0}
+    for rep in range(reps + 1):
+        for name, fn in calls:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fam.stream.wait_stream(torch.cuda.current_stream())
+            e0.record(fam.stream)
+            fn()
+            e1.record(fam.stream)
+            e1.synchronize()
+            if rep:
+                tot[name] += e0.elapsed_time(e1) / reps
+    return tot
+
+
+def char_leg(so_n=4000, so_steps=2000, dmr_steps=1000):
+    """Conservative against local characteristic variables for FAM5, the comparison of Table
+    runtime-main Panel B: a Shu-Osher-type 1D run ([-5, 5], OE Type II, CFL 0.2) and the double
+    Mach reflection (1440 x 480, limiter).  Each variant runs the same number of steps from the
+    same data (both tile heights autotuned in 2D); reported: ms per step (graph-replayed steps),
+    the RK stage launches (reconstruction, fluxes, quadrature: where the transform sits) and the
+    OE launch of one step at the final state, and the ratios characteristic / conservative."""
+    import dataclasses
+    import torch
+    import fam_inputs as fi
+    from paper_2609_26194_amd import Fam, FamConfig
+    cases = [
+        ("shu_osher", FamConfig(dim=1, nx=so_n, x0=-5.0, x1=5.0, k=5, system="euler", oe="type2", cfl=0.2,
+                                bc_x="transmissive"), fi.shu_osher(so_n), so_steps, so_n),
+        ("double_mach", FamConfig(dim=2, nx=1440, ny=480, x0=0.0, x1=3.0, y0=0.0, y1=1.0, k=5, system="euler",
+                                  oe="type2", cfl=0.2, pp=True, dmr=True), fi.double_mach(1440, 480), dmr_steps,
+         1440 * 480),
+    ]
+    res = {}
+    for name, cfg, U0h, nsteps, cells in cases:
+        U0 = torch.tensor(U0h, dtype=torch.float64).cuda()
+        row = {"cells": cells, "steps": nsteps}
+        for cv in (False, True):
+            fam = Fam(dataclasses.replace(cfg, char_vars=cv))
+            if cfg.dim == 2:
+                fam.autotune(U0)
+            U = U0.clone()
+            fam.run(U, 0.0, 5)   # warm-up
+            U.copy_(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            steps, _ = fam.run(U, 0.0, nsteps)
+            torch.cuda.synchronize()
+            elapsed = time.perf_counter() - t0
+            fam.check()
+            split = launch_split(fam, U)
+            fam.close()
+            row["characteristic" if cv else "conservative"] = {
+                "ms_per_step": elapsed / steps * 1e3, "cell_updates_per_s": cells * steps / elapsed,
+                "stage_launch_ms": split["stage"], "oe_launch_ms": split["oe"]}
+        c, w = row["conservative"], row["characteristic"]
+        row["ratio"] = {"total": w["ms_per_step"] / c["ms_per_step"],
+                        "stages": w["stage_launch_ms"] / c["stage_launch_ms"],
+                        "oe": w["oe_launch_ms"] / c["oe_launch_ms"]}
+        res[name] = row
+    return res
+
+
 def dmr_leg(t_final, nx=1440, ny=480):
     """The paper's double Mach reflection run: [0, 3] x [0, 1], 1440 x 480, FAM5, OE Type II,
     positivity limiter, CFL 0.2, to t_final; cell-updates/s and the split of one step's time
@@ -341,7 +413,6 @@ def dmr_leg(t_final, nx=1440, ny=480):
     import torch
     import fam_inputs as fi
     from paper_2609_26194_amd import Fam, FamConfig
-    from paper_2609_26194_amd.fam import fam_oe, fam_stage
     cfg = FamConfig(dim=2, nx=nx, ny=ny, x0=0.0, x1=3.0, y0=0.0, y1=1.0, k=5, system="euler", oe="type2",
                     cfl=0.2, pp=True, dmr=True)
     U0 = torch.tensor(fi.double_mach(nx, ny), dtype=torch.float64).cuda()
@@ -356,23 +427,7 @@ def dmr_leg(t_final, nx=1440, ny=480):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fam.check()
-    # one step's launches at the final state
-    dtd = fam.dt(U)
-    W1, W2, W3 = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
-    calls = [("stage", lambda: fam_stage(fam.h, 0, U, U, W1, dtd)), ("stage", lambda: fam_stage(fam.h, 1, U, W1, W2, dtd)),
-             ("stage", lambda: fam_stage(fam.h, 2, U, W2, W3, dtd)), ("oe", lambda: fam_oe(fam.h, W3, W1, dtd))]
-    tot = {"stage": 0.0, "oe": 0.0}
-    reps = 10
-    for rep in range(reps + 1):
-        for name, fn in calls:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            fam.stream.wait_stream(torch.cuda.current_stream())
-            e0.record(fam.stream)
-            fn()
-            e1.record(fam.stream)
-            e1.synchronize()
-            if rep:
-                tot[name] += e0.elapsed_time(e1) / reps
+    tot = launch_split(fam, U)
     fam.close()
     return {"workload": f"double Mach reflection {nx}x{ny} on [0,3]x[0,1], FAM5, OE Type II, positivity limiter, "
                         f"CFL 0.2, to t = {t:.4f}", "steps": steps, "cell_updates_per_s": nx * ny * steps / elapsed,
@@ -454,6 +509,9 @@ def main():
     if not args.no_dmr:
         log("double Mach reflection")
         out["dmr"] = dmr_leg(args.dmr_t)
+    if not args.no_char:
+        log("characteristic variables")
+        out["characteristic_variables"] = char_leg()
     if not args.no_adjoint:
         log("adjoint workload")
         out["adjoint"] = adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_checkpoint)

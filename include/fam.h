@@ -96,6 +96,15 @@ typedef struct {
                              pre-shock state beyond); states (rho, u, v, p) =
                              (8, 8.25 cos 30deg, -8.25 sin 30deg, 116.5) and
                              (1.4, 0, 0, 1).  bc_x, bc_y are ignored.  0 = off.  */
+  int char_vars;          /* Euler with k = 5 only: every RK stage reconstructs in
+                             the local characteristic variables of each cell's
+                             average (textbook eigenvectors of the x-direction flux
+                             Jacobian; L on the stencil moments, R on the
+                             coefficients), the FAM5 variant timed in Sec. 4.3
+                             (Table runtime-main, Panel B).  The reconstruction is
+                             linear, so the result is the conservative one up to
+                             rounding (Sec. 2.3); OE and the limiter are unchanged.
+                             0 = off.                                             */
 } fam_config;
 
 typedef struct fam_ctx fam_ctx;
@@ -106,8 +115,8 @@ fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx** out);
 /* A context advancing n_inst independent 2D instances together (one launch per
  * RK stage and one OE launch for all of them).  All instances share dim = 2,
  * k, system, gamma, oe, cfl and the boundary conditions; sizes and domains may
- * differ.  Every instance uses its own time step.  FAM_ERR_ARG for OE Type I
- * or the dmr boundaries (single contexts only). */
+ * differ.  Every instance uses its own time step.  FAM_ERR_ARG for OE Type I,
+ * the dmr boundaries or char_vars (single contexts only). */
 fam_status fam_init_batched(const fam_config* per_instance, int n_inst, void* hip_stream,
                             fam_ctx** out);
 
@@ -184,7 +193,7 @@ fam_status fam_set_tiling(fam_ctx* ctx, int stage_H, int oe_H);
  * |x|' = sign(x) with sign(0) = 0, maxima pass the derivative to their first
  * maximal entry, the zero-denominator branch of the OE coefficient has zero
  * derivative.  Synchronous.  Supported contexts: one 2D Euler instance,
- * periodic in x and y (no dmr boundaries), OE off or Type II, no positivity limiter, k = 6 with the
+ * periodic in x and y (no dmr boundaries, no char_vars), OE off or Type II, no positivity limiter, k = 6 with the
  * jumps of p_6; any other context returns FAM_ERR_STATE.  FAM_ERR_ARG for NULL
  * pointers, nsteps < 1, dt <= 0 or checkpoint_every < 1; FAM_ERR_NOMEM when the
  * checkpoints (ceil(nsteps / checkpoint_every) states) and the segment tape
@@ -200,7 +209,8 @@ fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
  *
  * fam_dbg_recon: point values of the stage reconstruction p_k of U (Sec. 2.4;
  *   eqs. 5 / 6, appendix coefficients; ghost cells per the boundary conditions;
- *   no positivity limiter) at every cell's flux points.  2D: NP = 32 points per
+ *   no positivity limiter; conservative variables also with char_vars, which
+ *   gives the same polynomial up to rounding) at every cell's flux points.  2D: NP = 32 points per
  *   cell and component: right face (1/2, eta_g), left face (-1/2, eta_g), top
  *   face (xi_g, 1/2), bottom face (xi_g, -1/2) for g = 0..3, then the volume
  *   nodes (xi_a, eta_b) at 16 + 4b + a; 1D: NP = 6: right face, left face, volume

@@ -1129,7 +1129,7 @@ extern "C" fam_status fam_adjoint(fam_ctx* c, const double* U0, int nsteps, doub
   if (!c || !U0 || !dJdU0 || nsteps < 1 || !(dt > 0.0) || checkpoint_every < 1) return FAM_ERR_ARG;
   const fam_config& f = c->cfg[0];
   if (c->ninst != 1 || c->dim != 2 || c->sys != FAM_EULER || f.bc_x != FAM_BC_PERIODIC ||
-      f.bc_y != FAM_BC_PERIODIC || f.dmr || c->oe == FAM_OE_TYPE1 || c->pp || (c->k == 6 && c->k6t))
+      f.bc_y != FAM_BC_PERIODIC || f.dmr || f.char_vars || c->oe == FAM_OE_TYPE1 || c->pp || (c->k == 6 && c->k6t))
     return FAM_ERR_STATE;
   switch (c->k) {
     case 3: return adjoint_k<3>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out);

@@ -62,6 +62,7 @@ static fam_status validate(const fam_config& c) {
   if (c.pp && !(c.system == FAM_EULER && c.dim == 2)) return FAM_ERR_ARG;
   if (c.dt_rule != 0 && c.dt_rule != 1) return FAM_ERR_ARG;
   if (c.dmr && !(c.system == FAM_EULER && c.dim == 2)) return FAM_ERR_ARG;
+  if (c.char_vars && !(c.system == FAM_EULER && c.k == 5)) return FAM_ERR_ARG;
   return FAM_OK;
 }
 
@@ -89,6 +90,7 @@ static Inst make_inst(const fam_ctx* c, int i) {
     in.ytop = f.y1;
     in.dmr_einv = 1.0 / (f.gamma - 1.0);
   }
+  in.charv = f.char_vars != 0;
   return in;
 }
 
@@ -311,7 +313,7 @@ extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_s
       return FAM_ERR_ARG;
   }
   if (per[0].oe == FAM_OE_TYPE1) return FAM_ERR_ARG;   // global statistics per instance: single contexts only
-  if (per[0].dmr) return FAM_ERR_ARG;   // the double Mach reflection boundaries: single contexts only
+  if (per[0].dmr || per[0].char_vars) return FAM_ERR_ARG;   // single-context options
   fam_ctx* c = new (std::nothrow) fam_ctx();
   if (!c) return FAM_ERR_NOMEM;
   c->cfg.assign(per, per + n);

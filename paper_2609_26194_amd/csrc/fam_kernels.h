@@ -34,6 +34,8 @@ struct Inst {
   const double* t_end;
   double t_ofs;
   double x0, ytop, dmr_einv;
+  // stage reconstruction in local characteristic variables (Euler, k = 5)
+  int charv;
 };
 
 struct StageArgs {

@@ -11,6 +11,7 @@
 // OE (Prop. 2.1, eq. 1dOE_system, Table sigma1d): jumps at both interfaces of the
 // cell, Type I / II denominator over Lambda_i = {i-1, i, i+1}, sigma = max over
 // components, u^(1) <- u^(1) exp(-beta dt sigma / dx).
+#include "fam_char.h"
 #include "fam_device.h"
 #include "fam_kernels.h"
 
@@ -58,7 +59,7 @@ __device__ __forceinline__ void load_tile1(Tile1& S, const double* __restrict__ 
   }
 }
 
-template <int K, class P>
+template <int K, class P, bool CHAR = false>
 __global__ void __launch_bounds__(T1) stage1d_kernel(StageArgs A, Inst in) {
   constexpr int NC = P::NC;
   __shared__ Tile1 S;
@@ -71,13 +72,49 @@ __global__ void __launch_bounds__(T1) stage1d_kernel(StageArgs A, Inst in) {
   load_tile1<NC>(S, A.Us, in, i0);
   __syncthreads();
   // reconstruction of cell i (LDS column t+1)
+  constexpr int NB = (K <= 4) ? (K == 3 ? 3 : 4) : (K == 5 ? 5 : 6);   // coefficients of p
   double cf[NC][6];
+  if constexpr (CHAR) {
+    // in the characteristic variables of this cell's average (L on the stencil,
+    // reconstruction per field, R on the coefficients)
+    double La[NC][NC], Ra[NC][NC];
+    {
+      double a[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    coeffs1d<K>(S.u[2 * c][t], S.u[2 * c][t + 1], S.u[2 * c][t + 2], S.u[2 * c + 1][t], S.u[2 * c + 1][t + 1],
-                S.u[2 * c + 1][t + 2], cf[c]);
+      for (int c = 0; c < NC; ++c) a[c] = S.u[2 * c][t + 1];
+      char_basis_x<1>(phys.g, a, La, Ra);
+    }
+#pragma unroll
+    for (int w = 0; w < NC; ++w) {
+      double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int o = 0; o < 3; ++o) v[3 * m + o] = fma(La[w][c], S.u[2 * c + m][t + o], v[3 * m + o]);
+      coeffs1d<K>(v[0], v[1], v[2], v[3], v[4], v[5], cf[w]);
+    }
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      double tw[NC];
+#pragma unroll
+      for (int w = 0; w < NC; ++w) tw[w] = cf[w][l];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double x = 0.0;
+#pragma unroll
+        for (int w = 0; w < NC; ++w) x = fma(Ra[c][w], tw[w], x);
+        cf[c][l] = x;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      coeffs1d<K>(S.u[2 * c][t], S.u[2 * c][t + 1], S.u[2 * c][t + 2], S.u[2 * c + 1][t], S.u[2 * c + 1][t + 1],
+                  S.u[2 * c + 1][t + 2], cf[c]);
+    }
   }
-  constexpr int NB = (K <= 4) ? (K == 3 ? 3 : 4) : (K == 5 ? 5 : 6);
   double lt[NC], rt[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
@@ -318,6 +355,10 @@ void launch_zero_alpha(StepState* st, int ninst, int parity, hipStream_t s) {
 
 void launch_stage1d(int k, int sys, const StageArgs& A, const Inst& in, hipStream_t s) {
   const dim3 grid((in.nx + OUT1 - 1) / OUT1);
+  if (in.charv && sys == 2 && k == 5) {   // characteristic variables: Euler, FAM5
+    hipLaunchKernelGGL((stage1d_kernel<5, Euler<1>, true>), grid, dim3(T1), 0, s, A, in);
+    return;
+  }
   FAM_DISPATCH_P1(sys, FAM_DISPATCH_K1(k, hipLaunchKernelGGL((stage1d_kernel<KK, PP>), grid, dim3(T1), 0, s, A, in)));
 }
 void launch_oe1d(int k, int sys, const OEArgs& A, const Inst& in, hipStream_t s) {

@@ -31,6 +31,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "fam_char.h"
 #include "fam_device.h"
 #include "fam_eval.h"
 #include "fam_kernels.h"
@@ -244,7 +245,7 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
 // ---------------------------------------------------------------------------
 // stage tile
 // ---------------------------------------------------------------------------
-template <int K, class P, bool PP, bool DMR = false>
+template <int K, class P, bool PP, bool DMR = false, bool CHAR = false>
 __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, int i0, int j0, int H,
                            Window& W, PPStage& PS, double& amax_x, double& amax_y, bool& bad) {
   constexpr int NC = P::NC;
@@ -304,15 +305,62 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 
     // reconstruction of all components
     double cf[NC][NCF];
+    if constexpr (CHAR) {
+      // in the characteristic variables of this cell's average: transform the
+      // stencil with L, reconstruct each field, map the coefficients back with R
+      double La[NC][NC], Ra[NC][NC];
+      {
+        double a[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double u0[9], u1[9], u2[9];
-      gather<K>(W, c, col, sl, sm, sh, u0, u1, u2);
-      double tmp[23];
-      coeffs2d<K>(u0, u1, u2, tmp, false);
+        for (int c = 0; c < NC; ++c) a[c] = W.v[sm][c * 3][col];
+        char_basis_x<2>(phys.g, a, La, Ra);
+      }
 #pragma unroll
-      for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
-      FAM_SCHED_FENCE();
+      for (int w = 0; w < NC; ++w) {
+        double u0[9], u1[9], u2[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) u0[l] = u1[l] = u2[l] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          double g0[9], g1[9], g2[9];
+          gather<K>(W, c, col, sl, sm, sh, g0, g1, g2);
+#pragma unroll
+          for (int l = 0; l < 9; ++l) {
+            u0[l] = fma(La[w][c], g0[l], u0[l]);
+            u1[l] = fma(La[w][c], g1[l], u1[l]);
+            u2[l] = fma(La[w][c], g2[l], u2[l]);
+          }
+        }
+        double tmp[23];
+        coeffs2d<K>(u0, u1, u2, tmp, false);
+#pragma unroll
+        for (int l = 0; l < NCF; ++l) cf[w][l] = tmp[l];
+        FAM_SCHED_FENCE();
+      }
+#pragma unroll
+      for (int l = 0; l < NCF; ++l) {
+        double t[NC];
+#pragma unroll
+        for (int w = 0; w < NC; ++w) t[w] = cf[w][l];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          double v = 0.0;
+#pragma unroll
+          for (int w = 0; w < NC; ++w) v = fma(Ra[c][w], t[w], v);
+          cf[c][l] = v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double u0[9], u1[9], u2[9];
+        gather<K>(W, c, col, sl, sm, sh, u0, u1, u2);
+        double tmp[23];
+        coeffs2d<K>(u0, u1, u2, tmp, false);
+#pragma unroll
+        for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
+        FAM_SCHED_FENCE();
+      }
     }
 
     // optional positivity limiter on this cell's reconstruction
@@ -677,7 +725,7 @@ __device__ __forceinline__ int heavy_first_slot(int L, int N, int nh) {
   return nh + base + (L - first) / NXCD;
 }
 
-template <int K, class P, bool PP, bool DMR>
+template <int K, class P, bool PP, bool DMR, bool CHAR = false>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
   __shared__ PPStage PS;
@@ -701,7 +749,7 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
     i0 = (T % gridDim.x) * STRIP;
     j0 = (T / gridDim.x) * H;
   }
-  stage_tile<K, P, PP, DMR>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
+  stage_tile<K, P, PP, DMR, CHAR>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
   if constexpr (PP) {
     if (threadIdx.x == 0) A.tile_work[tile] = PS.nwork;
@@ -746,7 +794,7 @@ __global__ void tile_identity_kernel(int* __restrict__ perm, int* __restrict__ w
   }
 }
 
-template <int K, class P, bool DMR>
+template <int K, class P, bool DMR, bool CHAR = false>
 __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const int4* __restrict__ seg,
                                                     const int* __restrict__ nseg) {
   __shared__ Window W;
@@ -761,7 +809,7 @@ __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const i
   double amx = 0.0, amy = 0.0;
   bool bad = false;
   PS.nwork = 0;
-  stage_tile<K, P, true, DMR>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
+  stage_tile<K, P, true, DMR, CHAR>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
 }
 
@@ -1102,24 +1150,31 @@ static bool dmr_of(const Inst& in) {
   else
     return false;
 }
-template <int K, class P, bool DMR>
+template <int K, class P, bool DMR, bool CHAR = false>
 static void launch_stage2d_d(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   dim3 grid((in.nx + STRIP - 1) / STRIP, (in.ny + H - 1) / H);
   if (A.pp) {
     const int ntiles = grid.x * grid.y;
-    hipLaunchKernelGGL((stage2d_kernel<K, P, true, DMR>), dim3(ntiles), dim3(LANES), 0, s, A, in, H);
+    hipLaunchKernelGGL((stage2d_kernel<K, P, true, DMR, CHAR>), dim3(ntiles), dim3(LANES), 0, s, A, in, H);
     // up to one tile per wave slot of the chip every tile starts at once: the
     // order stays the identity set with the tile height
     if (ntiles > ORDER_MIN_TILES)
       hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, A.tile_work, const_cast<int*>(A.tile_perm),
                          ntiles);
   } else {
-    hipLaunchKernelGGL((stage2d_kernel<K, P, false, DMR>), grid, dim3(LANES), 0, s, A, in, H);
+    hipLaunchKernelGGL((stage2d_kernel<K, P, false, DMR, CHAR>), grid, dim3(LANES), 0, s, A, in, H);
   }
 }
 template <int K, class P>
 static void launch_stage2d_t(const StageArgs& A, const Inst& in, int H, hipStream_t s) {
   if constexpr (std::is_same_v<P, Euler<2>>) {
+    // characteristic variables: FAM5 only (the variant the paper times)
+    if constexpr (K == 5) {
+      if (in.charv) {
+        if (dmr_of<P>(in)) return launch_stage2d_d<K, P, true, true>(A, in, H, s);
+        return launch_stage2d_d<K, P, false, true>(A, in, H, s);
+      }
+    }
     if (dmr_of<P>(in)) return launch_stage2d_d<K, P, true>(A, in, H, s);
   }
   launch_stage2d_d<K, P, false>(A, in, H, s);
@@ -1175,6 +1230,17 @@ void launch_stage2d(int k, int sys, const StageArgs& A, const Inst& in, int H, h
 template <int K, class P>
 static void launch_stage2d_list_t(const StageArgs& A, const Inst& in, const int4* seg, const int* nseg, int budget,
                                   hipStream_t s) {
+  if constexpr (std::is_same_v<P, Euler<2>> && K == 5) {
+    if (in.charv) {
+      if (dmr_of<P>(in))
+        hipLaunchKernelGGL((stage2d_list_kernel<K, P, true, true>), dim3(budget), dim3(LANES), 0, s, A, in, seg,
+                           nseg);
+      else
+        hipLaunchKernelGGL((stage2d_list_kernel<K, P, false, true>), dim3(budget), dim3(LANES), 0, s, A, in, seg,
+                           nseg);
+      return;
+    }
+  }
   if constexpr (std::is_same_v<P, Euler<2>>) {
     if (dmr_of<P>(in)) {
       hipLaunchKernelGGL((stage2d_list_kernel<K, P, true>), dim3(budget), dim3(LANES), 0, s, A, in, seg, nseg);

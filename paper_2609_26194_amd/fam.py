@@ -43,6 +43,7 @@ class _CConfig(ctypes.Structure):
         ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("oe", ctypes.c_int),
         ("oe_gamma_k", ctypes.c_double), ("cfl", ctypes.c_double), ("k6_jump_from_table", ctypes.c_int),
         ("pp", ctypes.c_int), ("dt_rule", ctypes.c_int), ("dmr", ctypes.c_int),
+        ("char_vars", ctypes.c_int),
     ]
 
 
@@ -69,12 +70,14 @@ class FamConfig:
     pp: bool = False
     dt_rule: int = 0
     dmr: bool = False
+    char_vars: bool = False
 
     def to_c(self):
         return _CConfig(self.dim, self.nx, self.ny if self.dim == 2 else 1, self.x0, self.x1, self.y0, self.y1,
                         self.k, SYSTEMS[self.system], self.gamma, float(self.a[0]), float(self.a[1]),
                         BCS[self.bc_x], BCS[self.bc_y], OES[self.oe], self.oe_gamma_k, self.cfl,
-                        int(self.k6_jump_from_table), int(self.pp), int(self.dt_rule), int(self.dmr))
+                        int(self.k6_jump_from_table), int(self.pp), int(self.dt_rule), int(self.dmr),
+                        int(self.char_vars))
 
     @property
     def ncomp(self):

@@ -50,7 +50,8 @@ def test_invalid_configurations_are_rejected_without_a_device():
                 dict(dim=2, nx=8, ny=8, cfl=0.0), dict(dim=2, nx=8, ny=8, gamma=1.0),
                 dict(dim=2, nx=8, ny=8, x0=1.0, x1=0.0), dict(dim=2, nx=65536, ny=32769),
                 dict(dim=1, nx=2), dict(dim=1, nx=8, pp=True), dict(dim=2, nx=8, ny=8, system="advection", dmr=True),
-                dict(dim=1, nx=8, system="euler", dmr=True), dict(dim=2, nx=8, ny=8, dt_rule=2)):
+                dict(dim=1, nx=8, system="euler", dmr=True), dict(dim=2, nx=8, ny=8, dt_rule=2),
+                dict(dim=2, nx=8, ny=8, k=4, char_vars=True), dict(dim=1, nx=8, system="burgers", char_vars=True)):
         cfg = FamConfig(**bad)
         assert lib.fam_init(ctypes.byref(cfg.to_c()), None, ctypes.byref(h)) == FAM_ERR_ARG
     # enum values outside their range
@@ -60,7 +61,7 @@ def test_invalid_configurations_are_rejected_without_a_device():
         assert lib.fam_init(ctypes.byref(c), None, ctypes.byref(h)) == FAM_ERR_ARG
     assert lib.fam_init(None, None, ctypes.byref(h)) == FAM_ERR_ARG
     # batched contexts: OE Type I and the double Mach reflection boundaries are single-context options
-    for extra in (dict(oe="type1"), dict(system="euler", dmr=True, x1=3.0)):
+    for extra in (dict(oe="type1"), dict(system="euler", dmr=True, x1=3.0), dict(system="euler", char_vars=True)):
         arr = (type(FamConfig(dim=2, nx=8, ny=8).to_c()) * 2)(*[FamConfig(dim=2, nx=8, ny=8, **extra).to_c()] * 2)
         assert lib.fam_init_batched(arr, 2, None, ctypes.byref(h)) == FAM_ERR_ARG
     assert lib.fam_step(None, None, 0.0, None) == FAM_ERR_ARG
