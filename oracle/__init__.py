@@ -28,8 +28,12 @@ cites without stating it; it is pinned by invariants (identity on admissible
 data, admissible and average-preserving output, tightness of the scaling).
 The double Mach reflection boundary data (``Config.dmr``; time-dependent
 ghost cells at each RK stage's time) follow the example's statement in Sec. 4
-with cell-centre assignment at the shock; parity unpinned beyond the scheme's
-invariants (the paper prints only a figure for this example).
+with cell-centre assignment at the shock.  The boundary data are pinned by the
+physics they describe (the two states satisfy the Rankine-Hugoniot conditions of a
+shock of normal speed 10, the top boundary switches where that shock meets the upper
+edge, the wall ghosts are the quadrature moments of the mirrored field); the run
+itself has no printed values (the paper prints only a figure), so its results are
+pinned by the scheme's invariants only.
 The local characteristic-variable stage reconstruction (``Config.char_vars``,
 the FAM5 alternative timed in Sec. 4.3) transforms each cell's stencil with the
 textbook left eigenvectors of the x-direction flux Jacobian at the cell's own
