@@ -95,3 +95,24 @@ def test_reflecting_wall_ghosts_are_moments_of_the_mirrored_field():
     for c in range(4):
         assert np.all(P[c, 0, 0:2, 2:-2][:, ~wall] == post[c])
         assert np.all(P[c, 1:, 0:2, 2:-2][..., ~wall] == 0.0)
+
+
+def test_shu_osher_left_state_is_the_mach3_post_shock_state():
+    """The Shu-Osher-type workload's left state (printed to 6-7 digits) and the gas at rest
+    ahead of it, (1, 0, 1), satisfy the 1D Rankine-Hugoniot conditions of a shock moving
+    right at Mach 3 (speed 3 sqrt(1.4)), to the printed precision."""
+    rl, ul, pl = fi.SHU_OSHER_LEFT
+    g = 1.4
+    s = 3.0 * math.sqrt(g * 1.0 / 1.0)
+
+    def F(rho, u, p):
+        E = p / (g - 1.0) + 0.5 * rho * u * u
+        return np.array([rho * u, rho * u * u + p, (E + p) * u]) - s * np.array([rho, rho * u, E])
+
+    left, right = F(rl, ul, pl), F(1.0, 0.0, 1.0)
+    assert np.max(np.abs(left - right) / np.abs(right)) < 5e-6   # p is printed as 10.33333
+    # and the printed values are those of the exact Mach 3 jump to their last digit
+    M2 = 9.0
+    assert abs(rl - (g + 1) * M2 / ((g - 1) * M2 + 2)) < 1e-6
+    assert abs(pl - (2 * g * M2 - (g - 1)) / (g + 1)) < 1e-5
+    assert abs(ul - s * (1.0 - 1.0 / ((g + 1) * M2 / ((g - 1) * M2 + 2)))) < 1e-6
