@@ -3,7 +3,7 @@
 One oracle step of each of:
 
 * the 2D Euler four-quadrant workload (2048 x 2048, seed 0, transmissive, CFL 0.2, OE
-  Type II, k = 5) with the positivity limiter on, as the benchmark runs it;
+  Type II, k = 5 and k = 6) with the positivity limiter on, as the benchmark runs it;
 * the double Mach reflection at the paper's size (1440 x 480 on [0, 3] x [0, 1], k = 5,
   OE Type II, limiter, CFL 0.2) from t = 0.
 
@@ -12,7 +12,7 @@ boundary rows and columns, the discontinuities of the initial data, 300 cells fr
 numpy's PCG64 with seed 78) plus up to 256 cells, in the order of their linear
 index, whose stage-0 reconstruction the oracle's limiter scales (theta < 1).
 
-Usage: python tests/golden/make_fullsize_limiter_samples.py   (a few minutes)
+Usage: python tests/golden/make_fullsize_limiter_samples.py   (about five minutes)
 """
 import os
 import sys
@@ -78,6 +78,11 @@ def main():
                    oe="type2", cfl=0.2, pp=True)
     for key, v in run_case(cfg, torch.tensor(fi.four_quadrant(2048, 0)), (1024,), (1024,), 78).items():
         out["c3pp_" + key] = v
+    print("four-quadrant 2048^2, k = 6, limiter", flush=True)
+    cfg = S.Config(dim=2, nx=2048, ny=2048, k=6, system="euler", bc_x="transmissive", bc_y="transmissive",
+                   oe="type2", cfl=0.2, pp=True)
+    for key, v in run_case(cfg, torch.tensor(fi.four_quadrant(2048, 0)), (1024,), (1024,), 78).items():
+        out["c3pp6_" + key] = v
     print("double Mach reflection 1440 x 480, k = 5, limiter", flush=True)
     cfg = S.Config(dim=2, nx=1440, ny=480, x0=0.0, x1=3.0, y0=0.0, y1=1.0, k=5, system="euler", oe="type2",
                    cfl=0.2, pp=True, dmr=True)

@@ -2,7 +2,7 @@
 benchmark times, against stored oracle samples (tests/golden/fullsize_limiter_one_step.npz,
 written by tests/golden/make_fullsize_limiter_samples.py from the oracle only).
 
-* 2048 x 2048 four-quadrant data (seed 0), k = 5, OE Type II, limiter: the tilings the
+* 2048 x 2048 four-quadrant data (seed 0), k = 5 and 6, OE Type II, limiter: the tilings the
   autotuner picks (as bench.py does) and the segment list, one step each.
 * The double Mach reflection at the paper's size, 1440 x 480, k = 5, limiter, from t = 0.
 
@@ -42,11 +42,12 @@ def _check(fam, U, gold, prefix):
 
 
 @pytest.mark.parametrize("tiling", ["autotuned", "segment_list"])
-def test_four_quadrant_2048_with_limiter(tiling):
+@pytest.mark.parametrize("k", [5, 6])
+def test_four_quadrant_2048_with_limiter(k, tiling):
     from paper_2609_26194_amd import Fam, FamConfig
     gold = np.load(GOLD)
-    log(f"four-quadrant 2048^2 k=5 limiter, {tiling}")
-    cfg = FamConfig(dim=2, nx=2048, ny=2048, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
+    log(f"four-quadrant 2048^2 k={k} limiter, {tiling}")
+    cfg = FamConfig(dim=2, nx=2048, ny=2048, k=k, system="euler", bc_x="transmissive", bc_y="transmissive",
                     oe="type2", cfl=0.2, pp=True)
     U0 = to_dev(fi.four_quadrant(2048, 0))
     fam = Fam(cfg)
@@ -54,7 +55,7 @@ def test_four_quadrant_2048_with_limiter(tiling):
         log(f"  autotuned tile heights {fam.autotune(U0)}")
     else:
         fam.set_tiling(0, 36)
-    _check(fam, U0.clone(), gold, "c3pp_")
+    _check(fam, U0.clone(), gold, "c3pp_" if k == 5 else "c3pp6_")
     fam.close()
 
 
