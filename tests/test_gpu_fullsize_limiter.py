@@ -6,6 +6,10 @@ written by tests/golden/make_fullsize_limiter_samples.py from the oracle only).
   autotuner picks (as bench.py does) and the segment list, one step each.
 * The double Mach reflection at the paper's size, 1440 x 480, k = 5, limiter, from t = 0.
 
+* The batched workload (256 instances, sizes from seed 1, data seeds 1000 + i, limiter),
+  autotuned as the benchmark runs it, one step: the first instance of each of the seven sizes
+  against the oracle's step of that instance (every cell).
+
 The samples hold the boundary rows and columns, the discontinuities of the initial
 data, random cells and up to 256 cells whose stage-0 reconstruction the oracle's
 limiter scales.  Bar: the time step to 1e-14 and every sampled moment within 1e-12 of
@@ -18,7 +22,8 @@ import pytest
 import torch
 
 import fam_inputs as fi
-from gpu_util import log, needs_gpu, to_dev
+import oracle.scheme as S
+from gpu_util import log, needs_gpu, rel_linf, to_dev
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 TOL = 1e-12
@@ -70,3 +75,30 @@ def test_double_mach_1440x480_with_limiter():
     log(f"  autotuned tile heights {fam.autotune(U0)}")
     _check(fam, U0.clone(), gold, "dmr_")
     fam.close()
+
+
+def test_batched_256_instances_with_limiter():
+    from paper_2609_26194_amd import Fam, FamConfig
+    sizes = fi.batch_sizes(256, 1)
+    kw = dict(dim=2, k=5, system="euler", bc_x="transmissive", bc_y="transmissive", oe="type2", cfl=0.2, pp=True)
+    cfgs = [FamConfig(nx=n, ny=n, **kw) for n in sizes]
+    states = [fi.batch_instance(i, n) for i, n in enumerate(sizes)]
+    bat = Fam(cfgs[0], batch=cfgs)
+    offs = bat.offsets()
+    U0 = torch.zeros(bat.len, dtype=torch.float64, device="cuda")
+    for o, st in zip(offs, states):
+        U0[o:o + st.size] = torch.as_tensor(st.reshape(-1)).cuda()
+    log(f"batched 256 instances ({sum(n * n for n in sizes)} cells), autotuned {bat.autotune(U0)}")
+    U = U0.clone()
+    bat.run(U, 0.0, 1)
+    bat.check()
+    firsts = {}
+    for i, n in enumerate(sizes):
+        firsts.setdefault(n, i)
+    for n, i in sorted(firsts.items()):
+        ref, _ = S.step(torch.tensor(states[i]), S.Config(nx=n, ny=n, **kw))
+        got = U[offs[i]:offs[i] + states[i].size].reshape(states[i].shape)
+        err = rel_linf(got, ref)
+        log(f"  instance {i} ({n}x{n}): rel Linf {err:.3e}")
+        assert err <= TOL
+    bat.close()
