@@ -197,7 +197,8 @@ fam_status fam_set_tiling(fam_ctx* ctx, int stage_H, int oe_H);
  * jumps of p_6; any other context returns FAM_ERR_STATE.  FAM_ERR_ARG for NULL
  * pointers, nsteps < 1, dt <= 0 or checkpoint_every < 1; FAM_ERR_NOMEM when the
  * checkpoints (ceil(nsteps / checkpoint_every) states) and the segment tape
- * (4 checkpoint_every states) do not fit; FAM_ERR_NONPHYSICAL if the forward
+ * (4 checkpoint_every states) do not fit (checkpoint_every >= nsteps records
+ * the whole run as one segment: no recomputation, a tape of 4 nsteps states); FAM_ERR_NONPHYSICAL if the forward
  * run meets an inadmissible state.  The scratch is kept for later calls and
  * freed by fam_destroy. */
 fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
