@@ -48,26 +48,26 @@ STAGE_SOURCES = ["fam_kernels2d.hip", "fam_device.h", "fam_eval.h", "fam_kernels
 
 def parse():
     p = argparse.ArgumentParser()
-    p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--n", type=int, default=2048)
-    p.add_argument("--k", type=int, default=5)
+    p.add_argument("--gpus", type=int, default=1, help="number of GPUs (only 1: the library runs a mesh or a batch on one GPU)")
+    p.add_argument("--steps", type=int, default=200, help="timed steps of the main workload")
+    p.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed region")
+    p.add_argument("--n", type=int, default=2048, help="mesh size n x n of the main workload")
+    p.add_argument("--k", type=int, default=5, help="order of the main workload")
     p.add_argument("--no-main", action="store_true", help="skip the main workload (profiling of the other legs)")
-    p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-n", type=int, default=512)
-    p.add_argument("--cpu-sample-steps", type=int, default=24)
+    p.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle baseline on the host")
+    p.add_argument("--cpu-sample-n", type=int, default=512, help="mesh size of the oracle baseline sample")
+    p.add_argument("--cpu-sample-steps", type=int, default=24, help="steps of the oracle baseline sample")
     p.add_argument("--no-k6", action="store_true", help="skip the k = 6 run of the main workload")
-    p.add_argument("--no-batched", action="store_true")
-    p.add_argument("--batched-steps", type=int, default=100)
-    p.add_argument("--no-adjoint", action="store_true")
-    p.add_argument("--adjoint-n", type=int, default=1024)
-    p.add_argument("--adjoint-steps", type=int, default=400)
-    p.add_argument("--adjoint-checkpoint", type=int, default=20)
+    p.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    p.add_argument("--batched-steps", type=int, default=100, help="steps of the batched workload")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    p.add_argument("--adjoint-n", type=int, default=1024, help="mesh size of the adjoint workload")
+    p.add_argument("--adjoint-steps", type=int, default=400, help="steps of the adjoint workload")
+    p.add_argument("--adjoint-checkpoint", type=int, default=20, help="checkpoint spacing of the adjoint workload")
     p.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
-    p.add_argument("--dmr-t", type=float, default=0.2)
+    p.add_argument("--dmr-t", type=float, default=0.2, help="final time of the double Mach reflection run")
     p.add_argument("--no-char", action="store_true", help="skip the characteristic-variable comparison")
-    p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), help="record the HBM traffic of the stage kernel from two rocprofv3 counter CSVs")
     return p.parse_args()
 
 
