@@ -79,3 +79,28 @@ def test_binding_rejects_wrong_sized_states():
     fake.cfgs = [None]
     with pytest.raises(ValueError):
         fake._state(torch.zeros(11, dtype=torch.float64))
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback path: without libfam.so the binding raises before any computation."""
+    from paper_2609_26194_amd import fam
+    monkeypatch.setattr(fam, "_lib", None)
+    monkeypatch.setattr(fam, "LIB_PATH", str(tmp_path / "libfam.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        fam.load_library()
+    # the context raises too (here first for the missing device, on a GPU box for the library)
+    with pytest.raises(RuntimeError):
+        fam.Fam(fam.FamConfig(dim=2, nx=8, ny=8))
+
+
+def test_ctypes_config_mirrors_the_header():
+    """The binding's fam_config has the header's fields, in the header's order."""
+    from paper_2609_26194_amd.fam import _CConfig
+    text = open(os.path.join(ROOT, "include", "fam.h")).read()
+    body = re.sub(r"/\*.*?\*/", "", text.split("typedef struct {", 1)[1].split("} fam_config;", 1)[0], flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            fields += [n.strip() for n in decl.split(None, 1)[1].split(",")]
+    assert [f for f, _ in _CConfig._fields_] == fields
