@@ -39,6 +39,8 @@ sys.path.insert(0, ROOT)
 # algorithmic HBM bytes per cell of one stage launch: stage 0 reads Us (12
 # doubles) and writes Uout (12); stages 1, 2 also read U0 (12)
 STAGE_BYTES = {0: 24 * 8, 1: 36 * 8, 2: 36 * 8}
+OE_BYTES = 20 * 8                 # OE reads the 12 moments, writes the 8 first moments
+STEP_BYTES = sum(STAGE_BYTES.values()) + OE_BYTES   # 928 B per cell-update
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6          # 256 CUs x 2.4 GHz x 128 FP64 flops / clock
 COPY_BYTES = 1 << 30             # calibration copy for the HBM counters
@@ -483,6 +485,9 @@ def main_workload(args, n, k):
     roofline = stage_roofline(fam, U, k, cells, seg_list=tuned[0] == 0)
     fam.close()
     copy_calibration()
+    # the whole step's algorithmic HBM rate: cell-updates/s x 928 B (three stages and the OE)
+    roofline["step_algorithmic_GBs"] = value * STEP_BYTES / 1e9
+    roofline["step_algorithmic_frac"] = value * STEP_BYTES / 1e9 / HBM_PEAK_GBS
     return {
         "metric": "2D Euler FAM cell-updates/s (FP64, k=5)",
         "value": value,
