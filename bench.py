@@ -164,9 +164,24 @@ def cpu_baseline(n, steps):
     for _ in range(steps):
         U, _ = step(U, cfg)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread (a smaller sample of the same recipe)
+    n1, steps1 = 256, 2
+    cfg1 = Config(dim=2, nx=n1, ny=n1, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
+                  oe="type2", cfl=0.2, pp=True)
+    torch.set_num_threads(1)
+    try:
+        V, _ = step(torch.tensor(fi.four_quadrant(n1, 0)), cfg1)  # warm-up
+        t1 = time.perf_counter()
+        for _ in range(steps1):
+            V, _ = step(V, cfg1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        torch.set_num_threads(threads)
     return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{n}x{n} cells of the same workload recipe, {steps} steps after one warm-up step "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "single_thread": {"value": n1 * n1 * steps1 / dt1, "cores": 1,
+                              "sample": f"{n1}x{n1} cells, {steps1} steps after one warm-up step ({dt1:.1f} s)"}}
 
 
 def stage_roofline(fam, U, k, cells, seg_list, reps=10):
