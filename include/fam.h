@@ -128,7 +128,9 @@ int fam_num_instances(const fam_ctx* ctx);
 
 /* One full step in place on U: CFL time step (unless dt_fixed > 0), three
  * SSP-RK3 stages, OE.  If dt_used_dev is not NULL the time step used is stored
- * there (device memory; one double per instance).  Asynchronous. */
+ * there (device memory; one double per instance).  Asynchronous.  Allocates
+ * nothing and enqueues only kernels and device-to-device copies on the
+ * context's stream, so it may be captured in a HIP graph and replayed. */
 fam_status fam_step(fam_ctx* ctx, double* U, double dt_fixed, double* dt_used_dev);
 
 /* Advance U in place until t_final (the last step clipped to land on it) or
