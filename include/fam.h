@@ -26,6 +26,13 @@
  * the adjoint's checkpoints and tapes), allocated in fam_init / fam_init_batched
  * / on the first fam_adjoint call and freed by fam_destroy.
  *
+ * Clock: a context keeps the simulation time of every instance, 0 after
+ * fam_init / fam_init_batched.  Every step advances it by its dt (fam_step,
+ * fam_run, and fam_dt, which begins a step for fam_stage / fam_oe); fam_set_time
+ * sets it.  The time enters the scheme only through time-dependent boundary data
+ * (the dmr boundaries' moving shock, evaluated at each RK stage's time).  The
+ * autotuner and the adjoint leave it unchanged.
+ *
  * Streams: all work is enqueued on the stream given to fam_init (NULL: the
  * default stream).  fam_step and fam_stage / fam_oe / fam_dt are asynchronous;
  * fam_run, fam_check and fam_adjoint synchronise the stream before returning.
@@ -127,21 +134,30 @@ size_t fam_instance_offset(const fam_ctx* ctx, int i);
 int fam_num_instances(const fam_ctx* ctx);
 
 /* One full step in place on U: CFL time step (unless dt_fixed > 0), three
- * SSP-RK3 stages, OE.  If dt_used_dev is not NULL the time step used is stored
+ * SSP-RK3 stages, OE; from the context clock's time t to t + dt (the clock
+ * advances).  If dt_used_dev is not NULL the time step used is stored
  * there (device memory; one double per instance).  Asynchronous.  Allocates
  * nothing and enqueues only kernels and device-to-device copies on the
  * context's stream, so it may be captured in a HIP graph and replayed. */
 fam_status fam_step(fam_ctx* ctx, double* U, double dt_fixed, double* dt_used_dev);
 
-/* Advance U in place until t_final (the last step clipped to land on it) or
+/* Advance U in place until the context clock reaches t_final (the last step
+ * clipped to land on it; nothing is done if the clock is already there) or
  * until max_steps steps, whichever comes first (t_final <= 0: max_steps steps).
  * dt_fixed > 0 replaces the CFL rule.  Steps are enqueued in chunks replayed
  * from a captured HIP graph; the stream is synchronised between chunks to test
  * for termination and non-physical states.  For a batched context every
  * instance runs to t_final (each with its own dt), and steps_done is the
- * largest per-instance count. */
+ * largest per-instance count of this call.  t_done (host, may be NULL): the
+ * clock at return (the smallest over instances). */
 fam_status fam_run(fam_ctx* ctx, double* U, double t_final, int max_steps, double dt_fixed,
                    int* steps_done, double* t_done);
+
+/* Set the context clock of every instance to t (for example back to 0 before
+ * running again from an initial state).  Asynchronous, on the context's stream
+ * (a kernel, so it may be captured too).  FAM_ERR_ARG for a NULL context or a
+ * t that is not finite. */
+fam_status fam_set_time(fam_ctx* ctx, double t);
 
 /* Building blocks of one step, for tests and profiling (asynchronous):
  * fam_dt:    dt_dev[inst] = CFL time step of U (or dt_fixed if > 0); also primes

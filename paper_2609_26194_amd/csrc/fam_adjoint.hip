@@ -1131,11 +1131,17 @@ extern "C" fam_status fam_adjoint(fam_ctx* c, const double* U0, int nsteps, doub
   if (c->ninst != 1 || c->dim != 2 || c->sys != FAM_EULER || f.bc_x != FAM_BC_PERIODIC ||
       f.bc_y != FAM_BC_PERIODIC || f.dmr || f.char_vars || c->oe == FAM_OE_TYPE1 || c->pp || (c->k == 6 && c->k6t))
     return FAM_ERR_STATE;
+  // the forward and recomputation passes step the context; its clock is put back
+  std::vector<double> clock;
+  fam_status r = save_clock(c, &clock);
+  if (r != FAM_OK) return r;
   switch (c->k) {
-    case 3: return adjoint_k<3>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out);
-    case 4: return adjoint_k<4>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out);
-    case 5: return adjoint_k<5>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out);
-    case 6: return adjoint_k<6>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out);
+    case 3: r = adjoint_k<3>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out); break;
+    case 4: r = adjoint_k<4>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out); break;
+    case 5: r = adjoint_k<5>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out); break;
+    case 6: r = adjoint_k<6>(c, U0, nsteps, dt, checkpoint_every, dJdUT, dJdU0, J_out); break;
+    default: return FAM_ERR_ARG;
   }
-  return FAM_ERR_ARG;
+  const fam_status rc = restore_clock(c, clock);
+  return r != FAM_OK ? r : rc;
 }

@@ -152,9 +152,28 @@ static fam_status init_steps(fam_ctx* c) {
   return FAM_OK;
 }
 
-// per run: time, step count, termination and wave-speed slots back to zero
+// per run: step count, termination and wave-speed slots back to zero; the
+// time of every instance (the context clock) is kept
 fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed) {
   fam::launch_reset_steps(c->st, c->ninst, t_final, dt_fixed, c->stream);
+  return FAM_OK;
+}
+
+// The clock of a synchronous call that steps internally (autotuner, adjoint)
+// is put back to what it was on entry.
+fam_status save_clock(fam_ctx* c, std::vector<double>* t) {
+  std::vector<StepState> h(c->ninst);
+  HIP_TRY(hipMemcpyAsync(h.data(), c->st, sizeof(StepState) * c->ninst, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  t->resize(c->ninst);
+  for (int i = 0; i < c->ninst; ++i) (*t)[i] = h[i].t;
+  return FAM_OK;
+}
+
+fam_status restore_clock(fam_ctx* c, const std::vector<double>& t) {
+  for (int i = 0; i < c->ninst; ++i) fam::launch_set_time(c->st + i, 1, t[i], c->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return FAM_OK;
 }
 
@@ -498,6 +517,12 @@ extern "C" fam_status fam_step(fam_ctx* c, double* U, double dt_fixed, double* d
   return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
 }
 
+extern "C" fam_status fam_set_time(fam_ctx* c, double t) {
+  if (!c || !std::isfinite(t)) return FAM_ERR_ARG;
+  fam::launch_set_time(c->st, c->ninst, t, c->stream);
+  return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
+}
+
 extern "C" fam_status fam_dt(fam_ctx* c, const double* U, double dt_fixed, double* dt_dev) {
   if (!c || !U || !dt_dev) return FAM_ERR_ARG;
   fam_status r = reset_steps(c, 0.0, 0.0);
@@ -592,7 +617,10 @@ extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* c
   if (!c || !U || reps < 1) return FAM_ERR_ARG;
   if (c->dim != 2) return FAM_OK;   // 1D launch shapes are fixed
   destroy_graphs(c);                // graphs hold the launch shapes they were captured with
-  fam_status r = reset_steps(c, 0.0, 0.0);
+  std::vector<double> clock;
+  fam_status r = save_clock(c, &clock);
+  if (r != FAM_OK) return r;
+  r = reset_steps(c, 0.0, 0.0);
   if (r != FAM_OK) return r;
   enqueue_alpha_full(c, U, 0);
   fam::launch_step_begin(c->st, c->ninst, 0, 0.0, 0.0, c->stream);
@@ -686,7 +714,7 @@ extern "C" fam_status fam_autotune(fam_ctx* c, const double* U, int reps, int* c
   HIP_TRY(hipStreamSynchronize(c->stream));
   int z = 0;
   HIP_TRY(hipMemcpy(c->flag, &z, sizeof(int), hipMemcpyHostToDevice));
-  return FAM_OK;
+  return restore_clock(c, clock);
 }
 
 extern "C" fam_status fam_check(fam_ctx* c) {
@@ -736,8 +764,12 @@ extern "C" fam_status fam_run(fam_ctx* c, double* U, double t_final, int max_ste
   std::vector<StepState> h(c->ninst);
   int done_steps = 0;
   double tmin = 0.0;
+  // With an end time, the first chunk is two steps; each later chunk holds the
+  // steps still needed at the last step's dt (at most 64, rounded up to even), so
+  // few replays past the end time are no-ops.
+  int next = tf > 0 ? 2 : limit;
   while (launched < limit) {
-    int chunk = std::min(limit - launched, tf > 0 ? 64 : limit);
+    const int chunk = std::min(limit - launched, next);
     const int pairs = chunk / 2;
     if (c->use_graph && pairs > 0) {
       hipGraphExec_t ex;
@@ -758,10 +790,13 @@ extern "C" fam_status fam_run(fam_ctx* c, double* U, double t_final, int max_ste
     bool all_done = true;
     done_steps = 0;
     tmin = 1e300;
+    double need = 0.0;
     for (auto& s : h) {
-      all_done &= (s.done != 0) || (tf > 0 && s.t >= tf);
+      const bool fin = (s.done != 0) || (tf > 0 && s.t >= tf);
+      all_done &= fin;
       done_steps = std::max(done_steps, s.steps);
       tmin = std::min(tmin, s.t);
+      if (!fin && s.dt > 0.0) need = std::max(need, std::ceil((tf - s.t) / s.dt));
     }
     int fl = 0;
     HIP_TRY(hipMemcpy(&fl, c->flag, sizeof(int), hipMemcpyDeviceToHost));
@@ -774,6 +809,10 @@ extern "C" fam_status fam_run(fam_ctx* c, double* U, double t_final, int max_ste
     }
     if (tf > 0 && all_done) break;
     if (chunk % 2) break;   // parity would break on another chunk; odd chunks only end a run
+    if (tf > 0) {
+      const int want = need > 62.0 ? 64 : std::max(2, (int)need);
+      next = want + (want & 1);
+    }
   }
   if (steps_done) *steps_done = done_steps;
   if (t_done) *t_done = tmin;

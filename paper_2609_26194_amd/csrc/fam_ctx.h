@@ -74,6 +74,8 @@ struct fam_ctx {
 fam_status set_stage_H(fam_ctx* c, int H);
 fam::Inst inst_for(const fam_ctx* c, int i, int parity, int stage);
 fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed);
+fam_status save_clock(fam_ctx* c, std::vector<double>* t);
+fam_status restore_clock(fam_ctx* c, const std::vector<double>& t);
 void enqueue_alpha_full(fam_ctx* c, const double* U, int parity);
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
                    const double* dt_override, bool repartition = true);

@@ -74,7 +74,7 @@ struct OEArgs {
 struct StepState {
   double alpha[2][3][2];   // [parity][stage input 0..2][x/y]
   double dt;               // time step of the current step
-  double t;                // time reached
+  double t;                // time reached: the context clock (0 at set-up, advanced by every step)
   double t_final;          // <= 0: none
   double dt_fixed;         // > 0: use instead of the CFL rule
   double cfl;
@@ -122,6 +122,9 @@ void launch_alpha1d(int sys, const PhysParams& pp, const double* U, const Inst& 
 // step bookkeeping: dt, clipping, termination, zeroing of the accumulators
 void launch_step_begin(StepState* st, int ninst, int parity, double dt_fixed, double t_final, hipStream_t s);
 void launch_zero_alpha(StepState* st, int ninst, int parity, hipStream_t s);
+// per run: wave-speed slots, dt, step count and termination back to zero; the
+// time (the context clock) is kept
 void launch_reset_steps(StepState* st, int ninst, double t_final, double dt_fixed, hipStream_t s);
+void launch_set_time(StepState* st, int ninst, double t, hipStream_t s);
 
 }  // namespace fam

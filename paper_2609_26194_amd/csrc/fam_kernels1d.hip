@@ -319,7 +319,6 @@ __global__ void reset_steps_kernel(StepState* st, int ninst, double t_final, dou
   for (int p = 0; p < 2; ++p)
     for (int q = 0; q < 3; ++q) s.alpha[p][q][0] = s.alpha[p][q][1] = 0.0;
   s.dt = 0.0;
-  s.t = 0.0;
   s.t_final = t_final;
   s.dt_fixed = dt_fixed;
   s.done = 0;
@@ -328,6 +327,17 @@ __global__ void reset_steps_kernel(StepState* st, int ninst, double t_final, dou
 
 void launch_reset_steps(StepState* st, int ninst, double t_final, double dt_fixed, hipStream_t s) {
   hipLaunchKernelGGL(reset_steps_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, st, ninst, t_final, dt_fixed);
+}
+
+// the context clock: every instance's time set to t (a kernel, not a memset, so a
+// captured graph may hold it)
+__global__ void set_time_kernel(StepState* st, int ninst, double t) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < ninst) st[id].t = t;
+}
+
+void launch_set_time(StepState* st, int ninst, double t, hipStream_t s) {
+  hipLaunchKernelGGL(set_time_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, st, ninst, t);
 }
 
 void launch_step_begin(StepState* st, int ninst, int parity, double dt_fixed, double t_final, hipStream_t s) {

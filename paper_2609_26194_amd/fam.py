@@ -109,6 +109,7 @@ def load_library():
         "fam_num_instances": (I, [VP]),
         "fam_step": (I, [VP, VP, D, VP]),
         "fam_run": (I, [VP, VP, D, I, D, ctypes.POINTER(I), P]),
+        "fam_set_time": (I, [VP, D]),
         "fam_dt": (I, [VP, VP, D, VP]),
         "fam_stage": (I, [VP, I, VP, VP, VP, VP]),
         "fam_oe": (I, [VP, VP, VP, VP]),
@@ -180,6 +181,10 @@ def fam_run(h, U, t_final=0.0, max_steps=0, dt_fixed=0.0):
     _check(load_library().fam_run(h, _ptr(U), float(t_final), int(max_steps), float(dt_fixed),
                                   ctypes.byref(n), ctypes.byref(t)), "fam_run")
     return n.value, t.value
+
+
+def fam_set_time(h, t):
+    _check(load_library().fam_set_time(h, float(t)), "fam_set_time")
 
 
 def fam_dt(h, U, dt_fixed, dt_dev):
@@ -300,6 +305,10 @@ class Fam:
     def run(self, U, t_final=0.0, max_steps=0, dt_fixed=0.0):
         self._state(U)
         return self._call(fam_run, U, t_final, max_steps, dt_fixed)
+
+    def set_time(self, t=0.0):
+        """Set the context clock (the time the next step starts from)."""
+        return self._call(fam_set_time, t)
 
     def dt(self, U, dt_fixed=0.0):
         self._state(U)

@@ -66,6 +66,7 @@ def test_invalid_configurations_are_rejected_without_a_device():
         assert lib.fam_init_batched(arr, 2, None, ctypes.byref(h)) == FAM_ERR_ARG
     assert lib.fam_step(None, None, 0.0, None) == FAM_ERR_ARG
     assert lib.fam_run(None, None, 1.0, 0, 0.0, None, None) == FAM_ERR_ARG
+    assert lib.fam_set_time(None, 0.0) == FAM_ERR_ARG
     assert lib.fam_dbg_recon(None, None, None) == FAM_ERR_ARG
     assert lib.fam_dbg_oe_factors(None, None, None, None) == FAM_ERR_ARG
 

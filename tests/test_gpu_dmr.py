@@ -73,3 +73,51 @@ def test_double_mach_rejected_where_unsupported():
         fam.dbg_recon(U)
     with pytest.raises(FamError):
         fam.adjoint(U, 2, 1e-4, 1)
+
+
+def test_double_mach_steps_continue_the_clock():
+    """The context clock carries the time from one call to the next: the top boundary's
+    moving shock is placed at each RK stage's time in every fam_step call and in every
+    replay of a captured fam_step, so N eager steps and N replays equal fam_run over N
+    steps bit for bit (and the oracle), after fam_set_time(0) brings the clock back."""
+    nx, ny, nsteps = 96, 32, 6
+    log(f"double Mach reflection {nx}x{ny}: fam_step / graph replays / fam_run over {nsteps} steps")
+    ora, cfg = both_configs(dim=2, nx=nx, ny=ny, x0=0.0, x1=3.0, y0=0.0, y1=1.0, k=5, system="euler", oe="type2",
+                            cfl=0.2, pp=True, dmr=True)
+    U0h = fi.double_mach(nx, ny)
+    U0 = to_dev(U0h)
+    fam = _fam(cfg)
+    Ur = U0.clone()
+    steps, t = fam.run(Ur, 0.0, nsteps)
+    fam.check()
+    assert steps == nsteps
+    ref, t_ref, _ = S.run(torch.tensor(U0h), ora, nsteps=nsteps)
+    assert abs(t - t_ref) <= 1e-14 and rel_linf(Ur, ref) <= TOL
+    # eager steps from the restarted clock
+    fam.set_time(0.0)
+    Ue = U0.clone()
+    for _ in range(nsteps):
+        fam.step(Ue)
+    torch.cuda.synchronize()
+    fam.check()
+    assert torch.equal(Ue, Ur)
+    # replays of one captured step
+    fam.set_time(0.0)
+    Ug = U0.clone()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=fam.stream):
+        fam.step(Ug)
+    torch.cuda.synchronize()
+    for _ in range(nsteps):
+        g.replay()
+    torch.cuda.synchronize()
+    fam.check()
+    assert torch.equal(Ug, Ur)
+    # the clock has reached the run's end time; a run to that time does nothing
+    Uz = Ur.clone()
+    n0, t0 = fam.run(Uz, t, 0)
+    assert n0 == 0 and torch.equal(Uz, Ur) and abs(t0 - t) <= 1e-15
+    log(f"  t = {t:.4e}: eager steps and replays equal fam_run bitwise; rel Linf vs oracle {rel_linf(Ur, ref):.2e}")
+    del g
+    fam.close()
