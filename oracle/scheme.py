@@ -434,14 +434,21 @@ def cfl_dt(U, cfg):
 STAGE_TIME = (0.0, 1.0, 0.5)   # stage s evaluates R at t_n + STAGE_TIME[s] dt
 
 
+RK3_C0 = (0.0, 0.75, 1.0 / 3.0)   # weight of U^n in stage s; L = U^s + dt R(U^s) gets 1 - c
+
+
 def rk3_stage(s, U0, Us, dt, cfg, t=0.0):
-    """Stage s (0, 1, 2) of the Shu-Osher form of SSP-RK3 (eq. 12); t = t_n (boundary data)."""
+    """Stage s (0, 1, 2) of the Shu-Osher form of SSP-RK3 (eq. 12); t = t_n (boundary data).
+
+    The convex combination c U0 + (1 - c) L is evaluated as L + c (U0 - L).  Written
+    with the two weights rounded separately, the last stage's 1/3 and 2/3 sum to
+    1 - 2^-54 in FP64, which shrinks every value by that factor in every step: on a
+    smooth run of 5.7e4 steps a bias of 3e-12 in the density, larger than the printed
+    FAM6 error of Table 1dEuler at N = 70 (the bias doubles when dt is halved)."""
     Ls = Us + dt * residual(Us, cfg, t + STAGE_TIME[s] * dt)
     if s == 0:
         return Ls
-    if s == 1:
-        return 0.75 * U0 + 0.25 * Ls
-    return U0 / 3.0 + (2.0 / 3.0) * Ls
+    return Ls + RK3_C0[s] * (U0 - Ls)
 
 
 def rk3(U0, dt, cfg, t=0.0):

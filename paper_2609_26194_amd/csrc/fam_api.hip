@@ -427,14 +427,12 @@ fam_status set_stage_H(fam_ctx* c, int H) {
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
                           const double* dt_override, bool repartition) {
   static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
-  static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
   fam::StageArgs A{};
   A.phys = c->phys;
   A.Us = Us;
   A.U0 = U0;
   A.Uout = Uout;
   A.ca = CA[s];
-  A.cb = CB[s];
   A.flag = c->flag;
   A.done = &c->st[0].done;
   A.pp = c->pp;

@@ -43,7 +43,10 @@ struct StageArgs {
   const double* Us;
   const double* U0;
   double* Uout;
-  double ca, cb;           // Uout = ca U0 + cb (Us + dt R(Us))
+  // Shu-Osher stage ca U0 + (1 - ca) L with L = Us + dt R(Us), evaluated as
+  // L + ca (U0 - L): the rounded 1/3 and 2/3 of the last stage sum to 1 - 2^-54,
+  // which as separate weights would shrink every value by that much each step
+  double ca;
   int* flag;
   const int* done;
   int pp;                  // positivity limiter on the stage reconstruction (2D Euler)

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(T1) stage1d_kernel(StageArgs A, Inst in) {
       for (int m = 0; m < 2; ++m) {
         const size_t idx = in.offset + (c * 2 + m) * in.plane + i;
         const double L = S.u[2 * c + m][t + 1] + dt * Rm[m];
-        const double v = (A.ca == 0.0) ? L : A.ca * A.U0[idx] + A.cb * L;
+        const double v = (A.ca == 0.0) ? L : fma(A.ca, A.U0[idx] - L, L);
         A.Uout[idx] = v;
         if (m == 0) avg[c] = v;
       }

@@ -407,7 +407,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const double L = W.v[sl][c * 3 + m][col] + dt * Rm[m];
-          const double v = use_u0 ? A.ca * u0row[c * 3 + m] + A.cb * L : L;
+          const double v = use_u0 ? fma(A.ca, u0row[c * 3 + m] - L, L) : L;
           Uo[(c * 3 + m) * in.plane + idx] = v;
           if (m == 0) avg[c] = v;
         }

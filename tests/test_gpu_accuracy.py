@@ -3,39 +3,23 @@
 
 Errors are the mean absolute error of the density (Burgers: u) cell averages
 against the exact cell averages at the final time; the printed values are the
-paper's (tests/golden/smooth_accuracy_tables.txt).  They are compared within the
-same factors as the oracle's own pins (Euler's averages sit 1.4-2x above the
-printed values for a reason not identified, while the first moments of the same
-runs match closely; Burgers FAM4 differs most) at every printed mesh size, the
-upper bound raised to the accumulated FP64 rounding of the run (steps x 2^-52 x
-max|u|) where FAM6 on the finest meshes reaches it.  The 2D table runs N = 20..80
-by default and 100, 120 with FAM_SLOW=1.  One run per system is
-also compared with the oracle step for step (the whole time-step sequence,
-including the dx^{k/3} rule and the clipped last step).
+paper's (tests/golden/smooth_accuracy_tables.txt).  The runs use the table reading
+of the OE constant (half the stated gamma_k, equivalently the mean of the two
+interface jumps; golden_util.table_gamma_k), under which every 1D row reproduces
+within the factors below at every printed mesh size.  Table 2dEuler: FAM3 within its factor; FAM4, FAM5 and FAM6 are
+a known gap (1.4x, 1.7-2.3x, 2.0-2.4x above the printed rows with OE on or off,
+i.e. not the OE's), pinned to bands of the measured ratios so a change in either
+direction shows.  The 2D table runs N = 20..80 by default and 100, 120 with
+FAM_SLOW=1.  One run per system is also compared with
+the oracle step for step (the whole time-step sequence, including the dx^{k/3}
+rule and the clipped last step).
 
 The appendix tables of first-moment errors (supp:1dBurMoment, supp:1dEulerMoment)
 are reproduced at every printed mesh size: the mean absolute error of the scaled
-first moment of the density (Burgers: u) within per-order factors of the printed
-value, and the observed order over the whole range of at least k - 0.5.
+first moment of the density (Burgers: u) within a factor of the printed value, and
+the observed order over the whole range of at least k - 0.5.
 """
 
-# the factor within which the first-moment errors reproduce the printed ones
-MOM_TOL = {3: 1.5, 4: 2.0, 5: 1.5, 6: 1.5}
-EPS = 2.0 ** -52
-
-
-def _rounding_floor(steps, umax):
-    """Accumulated FP64 rounding of a run: below steps * eps * max|u| an error cannot be told
-    from the printed one (FAM6 on the finest meshes reaches it after 5e4 - 3e5 steps)."""
-    return steps * EPS * umax
-
-
-def _check_avg(name, n, k, e, steps, tol, umax):
-    g = _gold(name, n, k)
-    hi = max(g * tol, _rounding_floor(steps, umax))
-    log(f"  {name} FAM{k} N={n}: {steps} steps, error {e:.3e} (printed {g:.3e}, ratio {e / g:.3f}, "
-        f"bound {hi:.2e})")
-    assert g / tol < e < hi
 import math
 import os
 
@@ -45,11 +29,33 @@ import torch
 
 import fam_inputs as fi
 import oracle.scheme as S
-from golden_util import parse_table
+from golden_util import parse_table, table_gamma_k
 from gpu_util import both_configs, log, needs_gpu, rel_linf, to_dev
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 GOLD = parse_table("smooth_accuracy_tables.txt")
+
+# the factors within which the errors reproduce the printed ones, per table and order;
+# measured ratios computed / printed over all printed N in the comments
+AVG_TOL = {"burgers_avg": {3: 1.25, 4: 1.25, 5: 1.25, 6: 1.25},     # 0.95-1.00, 0.92-0.95, 0.97-1.03, 0.98-1.02
+           "euler1d_avg": {3: 1.25, 4: 1.25, 5: 1.25, 6: 1.25},     # 1.00-1.02, 1.09-1.10, 1.00-1.05, 1.12-1.15
+           "euler2d_avg": {3: 1.25}}                                # 0.92-1.12
+MOM_TOL = {3: 1.25, 4: 1.25, 5: 1.25, 6: 1.25}                      # Euler 1.00-1.15; Burgers FAM3/4/6 0.97-1.19
+# Known gaps, each a band (lo, hi) of the ratio computed / printed that holds the measured
+# values, so a change in either direction shows.
+#  * Table 2dEuler FAM4, FAM5, FAM6 (N = 20..80): 1.36-1.42, 1.73-2.26, 2.04-2.19; with OE
+#    off 1.25-1.35, 1.65-2.26, 1.95-2.13 (N = 20..60), so the difference is not the OE's.
+#  * the Burgers FAM5 first moment from N = 90 on: 1.25, 1.28, 1.34, 1.39 (N = 90..180).
+GAPS = {("euler2d_avg", 4): (1.25, 1.6), ("euler2d_avg", 5): (1.5, 2.5), ("euler2d_avg", 6): (1.8, 2.6),
+        ("burgers_mom", 5, 90): (1.1, 1.5), ("burgers_mom", 5, 120): (1.1, 1.5), ("burgers_mom", 5, 150): (1.1, 1.6),
+        ("burgers_mom", 5, 180): (1.1, 1.6)}
+
+
+def _bounds(name, n, k, g, tol):
+    band = GAPS.get((name, k, n), GAPS.get((name, k)))
+    if band is not None:
+        return g * band[0], g * band[1]
+    return g / tol, g * tol
 
 
 def _gold(table, n, k):
@@ -57,6 +63,13 @@ def _gold(table, n, k):
         if name == table and nn == n:
             return vals[k - 3]
     raise KeyError((table, n))
+
+
+def _check_avg(name, n, k, e, steps):
+    g = _gold(name, n, k)
+    lo, hi = _bounds(name, n, k, g, AVG_TOL[name].get(k))
+    log(f"  {name} FAM{k} N={n}: {steps} steps, error {e:.3e} (printed {g:.3e}, ratio {e / g:.3f})")
+    assert lo < e < hi
 
 
 def _fam(cfg):
@@ -73,16 +86,16 @@ def _run(cfg, U0, T):
     return U.cpu().numpy(), steps
 
 
-@pytest.mark.parametrize("k,tol", [(3, 1.6), (4, 1.8), (5, 1.15), (6, 1.15)])
-def test_burgers_table(k, tol):
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_burgers_table(k):
     T = 0.5 / math.pi
     errs = []
     for n in (30, 60, 90, 120, 150, 180):
         _, cfg = both_configs(dim=1, nx=n, x0=0.0, x1=2.0, k=k, system="burgers", oe="type2", cfl=0.1,
-                              dt_rule=1)
+                              dt_rule=1, oe_gamma_k=table_gamma_k(1, k))
         U, steps = _run(cfg, fi.burgers_smooth(n), T)
         e = float(np.abs(U[0, 0] - fi.burgers_exact_moments(n, T)[0, 0]).mean())
-        _check_avg("burgers_avg", n, k, e, steps, tol, 1.5)
+        _check_avg("burgers_avg", n, k, e, steps)
         errs.append(e)
     order = math.log(errs[1] / errs[2]) / math.log(90 / 60)
     log(f"  order 60 -> 90: {order:.2f}")
@@ -92,10 +105,11 @@ def test_burgers_table(k, tol):
 @pytest.mark.parametrize("k", [3, 4, 5, 6])
 def test_euler_1d_table(k):
     for n in (20, 30, 40, 50, 60, 70):
-        _, cfg = both_configs(dim=1, nx=n, x0=0.0, x1=2.0, k=k, system="euler", oe="type2", cfl=0.1, dt_rule=1)
+        _, cfg = both_configs(dim=1, nx=n, x0=0.0, x1=2.0, k=k, system="euler", oe="type2", cfl=0.1, dt_rule=1,
+                              oe_gamma_k=table_gamma_k(1, k))
         U, steps = _run(cfg, fi.smooth_euler_1d(n), 2.0)
         e = float(np.abs(U[0, 0] - fi.smooth_euler_1d_exact_density(n, 2.0)[0, 0]).mean())
-        _check_avg("euler1d_avg", n, k, e, steps, 2.5, 1.2)
+        _check_avg("euler1d_avg", n, k, e, steps)
 
 
 EULER2D_N = (20, 40, 60, 80) + ((100, 120) if os.environ.get("FAM_SLOW") == "1" else ())
@@ -106,10 +120,10 @@ def test_euler_2d_table(k):
     """N = 20..80 by default; the 100 and 120 rows (3e5 steps at FAM6) with FAM_SLOW=1."""
     for n in EULER2D_N:
         _, cfg = both_configs(dim=2, nx=n, ny=n, x0=0.0, x1=2.0, y0=0.0, y1=2.0, k=k, system="euler", oe="type2",
-                              cfl=0.1, dt_rule=1)
+                              cfl=0.1, dt_rule=1, oe_gamma_k=table_gamma_k(2, k))
         U, steps = _run(cfg, fi.smooth_euler_2d(n), 2.0)
         e = float(np.abs(U[0, 0] - fi.smooth_euler_2d_exact_density(n, 2.0)[0, 0]).mean())
-        _check_avg("euler2d_avg", n, k, e, steps, 3.0, 1.2)
+        _check_avg("euler2d_avg", n, k, e, steps)
 
 
 @pytest.mark.parametrize("system,dim", [("burgers", 1), ("euler", 1), ("euler", 2)])
@@ -140,12 +154,13 @@ def _moment_table(table, k, ns, make, exact, T):
     errs = []
     for n in ns:
         _, cfg = both_configs(dim=1, nx=n, x0=0.0, x1=2.0, k=k, system="burgers" if table == "burgers_mom" else "euler",
-                              oe="type2", cfl=0.1, dt_rule=1)
+                              oe="type2", cfl=0.1, dt_rule=1, oe_gamma_k=table_gamma_k(1, k))
         U, steps = _run(cfg, make(n), T)
         e = float(np.abs(U[0, 1] - exact(n, T)[0, 1]).mean())
         g = _gold(table, n, k)
         log(f"  {table} FAM{k} N={n}: {steps} steps, first-moment error {e:.3e} (printed {g:.3e}, ratio {e / g:.3f})")
-        assert g / MOM_TOL[k] < e < g * MOM_TOL[k]
+        lo, hi = _bounds(table, n, k, g, MOM_TOL[k])
+        assert lo < e < hi
         errs.append(e)
     order = math.log(errs[0] / errs[-1]) / math.log(ns[-1] / ns[0])
     log(f"  order {ns[0]} -> {ns[-1]}: {order:.2f}")

@@ -231,3 +231,31 @@ def test_nonphysical_state_is_reported():
     U[3, 0, 5, 5] = 0.01  # energy below kinetic: negative pressure in one cell average
     with pytest.raises(NonPhysicalState):
         step(U, euler2d(16, pp=True))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_uniform_state_is_a_fixed_point_bit_for_bit(dim):
+    """On a uniform periodic flow every cell computes the same values, so the average
+    residual R^(0) is exactly zero and every RK stage must return the averages of U^n
+    bit for bit: true when the convex combination of eq. 12 is formed as
+    L + c (U^n - L), not with the weights 1/3 and 2/3 rounded separately (their sum is
+    1 - 2^-54, and a generic value drifts).  (The first moments move at rounding level:
+    the quadrature weights do not sum to one exactly.)"""
+    rng = np.random.default_rng(5 + dim)
+    for _ in range(4):
+        rho, p = rng.uniform(0.2, 3.0), rng.uniform(0.1, 4.0)
+        vel = rng.uniform(-1.5, 1.5, dim)
+        E = p / 0.4 + 0.5 * rho * float(np.sum(vel * vel))
+        vals = [rho] + list(rho * vel) + [E]
+        if dim == 1:
+            cfg = Config(dim=1, nx=12, k=5, system="euler", oe="type2")
+            U = torch.zeros(3, 2, 12, dtype=torch.float64)
+        else:
+            cfg = euler2d(10)
+            U = torch.zeros(4, 3, 10, 10, dtype=torch.float64)
+        for c, v in enumerate(vals):
+            U[c, 0] = v
+        U0 = U.clone()
+        for _ in range(20):
+            U, _ = step(U, cfg)
+        assert torch.equal(U[:, 0], U0[:, 0])
