@@ -57,7 +57,8 @@ typedef enum {
   FAM_ERR_DEVICE = -2,       /* a HIP call failed                            */
   FAM_ERR_NOMEM = -3,        /* device allocation failed                     */
   FAM_ERR_NONPHYSICAL = -4,  /* inadmissible cell average met (device flag)  */
-  FAM_ERR_STATE = -5         /* call not valid for this context              */
+  FAM_ERR_STATE = -5,        /* call not valid for this context              */
+  FAM_ERR_SIZE = -6          /* problem larger than fam_step_static's scratch */
 } fam_status;
 
 typedef enum { FAM_ADVECTION = 0, FAM_BURGERS = 1, FAM_EULER = 2 } fam_system;
@@ -243,6 +244,30 @@ fam_status fam_adjoint(fam_ctx* ctx, const double* U0, int nsteps, double dt,
  *   caller buffer.  FAM_ERR_STATE with OE off. */
 fam_status fam_dbg_recon(fam_ctx* ctx, const double* U, double* vals);
 fam_status fam_dbg_oe_factors(fam_ctx* ctx, const double* Un, const double* dt_dev, double* delta);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): one full step in place
+ * on U, as fam_step on a fresh context for cfg (same kernels and launch shapes,
+ * the same result bit for bit), without a context and without allocating.
+ * cfg: as for fam_init (single instance).  hip_stream: hipStream_t or NULL.
+ * U: device state in the layout above (caller-owned).  t: the time at the start
+ * of the step (it enters only through time-dependent boundary data: the dmr
+ * boundaries).  dt_fixed > 0 replaces the CFL rule.  dt_used_dev (device, may be
+ * NULL): receives the step's dt.  flag_dev (device int, may be NULL): 1 is ORed
+ * into it when a non-physical cell average is met (the caller clears it; NULL:
+ * the condition is not reported).  Asynchronous; enqueues only kernels and one
+ * device-to-device copy of dt.
+ * Scratch: a device array of FAM_STATIC_SCRATCH_BYTES on each GPU the library
+ * runs on, held until the process ends (the two SSP-RK3 stage states and the
+ * step's reduction slots): states of at most (FAM_STATIC_SCRATCH_BYTES -
+ * 256 KiB) / 16 doubles, e.g. a 2D Euler mesh of 512 x 512 cells; larger ones
+ * return FAM_ERR_SIZE before anything is enqueued.  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  FAM_ERR_ARG for a NULL
+ * cfg or U, an invalid cfg, a t that is not finite or a NaN dt_fixed. */
+#define FAM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+fam_status fam_step_static(const fam_config* cfg, void* hip_stream, double* U, double t, double dt_fixed,
+                           double* dt_used_dev, int* flag_dev);
 
 void fam_destroy(fam_ctx* ctx);
 const char* fam_status_str(fam_status s);

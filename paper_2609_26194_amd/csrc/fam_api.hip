@@ -39,6 +39,7 @@ extern "C" const char* fam_status_str(fam_status s) {
     case FAM_ERR_NOMEM: return "out of device memory";
     case FAM_ERR_NONPHYSICAL: return "non-physical state (rho <= 0 or p <= 0 in a cell average)";
     case FAM_ERR_STATE: return "call not valid for this context";
+    case FAM_ERR_SIZE: return "problem larger than the static scratch of fam_step_static";
   }
   return "unknown status";
 }
@@ -48,7 +49,7 @@ extern "C" const char* fam_status_str(fam_status s) {
     if ((expr) != hipSuccess) return FAM_ERR_DEVICE; \
   } while (0)
 
-static fam_status validate(const fam_config& c) {
+fam_status validate_config(const fam_config& c) {
   if (c.dim != 1 && c.dim != 2) return FAM_ERR_ARG;
   if (c.nx < 3 || (c.dim == 2 && c.ny < 3)) return FAM_ERR_ARG;
   if (c.k < 3 || c.k > 6) return FAM_ERR_ARG;
@@ -66,7 +67,7 @@ static fam_status validate(const fam_config& c) {
   return FAM_OK;
 }
 
-static double default_gamma_k(int dim, int k) {
+double default_gamma_k(int dim, int k) {
   if (dim == 1) return k <= 4 ? 25.0 : 12.5;
   return k <= 4 ? 25.0 : 15.0;
 }
@@ -112,7 +113,7 @@ Inst inst_for(const fam_ctx* c, int i, int parity, int stage) {
 }
 
 // rows per strip tile: enough tiles to fill 256 CUs several times over
-static int choose_H(int nx, int ny) {
+int choose_H(int nx, int ny) {
   const int strips = (nx + fam::STRIP - 1) / fam::STRIP;
   int H = 32;
   while (H > 8 && (size_t)strips * ((ny + H - 1) / H) < 8 * 256) H /= 2;
@@ -239,7 +240,7 @@ static void set_common(fam_ctx* c, const fam_config& f) {
 extern "C" fam_status fam_init(const fam_config* cfg, void* hip_stream, fam_ctx** out) {
   if (!cfg || !out) return FAM_ERR_ARG;
   *out = nullptr;
-  fam_status v = validate(*cfg);
+  fam_status v = validate_config(*cfg);
   if (v != FAM_OK) return v;
   fam_ctx* c = new (std::nothrow) fam_ctx();
   if (!c) return FAM_ERR_NOMEM;
@@ -323,7 +324,7 @@ extern "C" fam_status fam_init_batched(const fam_config* per, int n, void* hip_s
   if (!per || !out || n < 1) return FAM_ERR_ARG;
   *out = nullptr;
   for (int i = 0; i < n; ++i) {
-    fam_status v = validate(per[i]);
+    fam_status v = validate_config(per[i]);
     if (v != FAM_OK) return v;
     const fam_config &a = per[0], &b = per[i];
     if (b.dim != 2 || b.k != a.k || b.system != a.system || b.gamma != a.gamma || b.oe != a.oe ||

@@ -71,6 +71,9 @@ struct fam_ctx {
 };
 
 
+fam_status validate_config(const fam_config& c);
+double default_gamma_k(int dim, int k);
+int choose_H(int nx, int ny);   // default strip-tile height of a 2D mesh
 fam_status set_stage_H(fam_ctx* c, int H);
 fam::Inst inst_for(const fam_ctx* c, int i, int parity, int stage);
 fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed);

@@ -18,7 +18,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfam.so")
 
-FAM_OK, FAM_ERR_ARG, FAM_ERR_DEVICE, FAM_ERR_NOMEM, FAM_ERR_NONPHYSICAL, FAM_ERR_STATE = 0, -1, -2, -3, -4, -5
+FAM_OK, FAM_ERR_ARG, FAM_ERR_DEVICE, FAM_ERR_NOMEM, FAM_ERR_NONPHYSICAL, FAM_ERR_STATE, FAM_ERR_SIZE = \
+    0, -1, -2, -3, -4, -5, -6
 SYSTEMS = {"advection": 0, "burgers": 1, "euler": 2}
 BCS = {"periodic": 0, "transmissive": 1}
 OES = {"off": 0, "type1": 1, "type2": 2}
@@ -110,6 +111,7 @@ def load_library():
         "fam_step": (I, [VP, VP, D, VP]),
         "fam_run": (I, [VP, VP, D, I, D, ctypes.POINTER(I), P]),
         "fam_set_time": (I, [VP, D]),
+        "fam_step_static": (I, [ctypes.POINTER(_CConfig), VP, VP, D, D, VP, VP]),
         "fam_dt": (I, [VP, VP, D, VP]),
         "fam_stage": (I, [VP, I, VP, VP, VP, VP]),
         "fam_oe": (I, [VP, VP, VP, VP]),
@@ -181,6 +183,15 @@ def fam_run(h, U, t_final=0.0, max_steps=0, dt_fixed=0.0):
     _check(load_library().fam_run(h, _ptr(U), float(t_final), int(max_steps), float(dt_fixed),
                                   ctypes.byref(n), ctypes.byref(t)), "fam_run")
     return n.value, t.value
+
+
+def fam_step_static(cfg, stream_handle, U, t=0.0, dt_fixed=0.0, dt_used=None, flag=None):
+    """One step on U without a context or any allocation (fam.h); flag: int32 GPU tensor or None."""
+    if flag is not None and not (flag.is_cuda and flag.dtype == torch.int32):
+        raise ValueError("flag: an int32 GPU tensor")
+    fp = None if flag is None else ctypes.c_void_p(flag.data_ptr())
+    _check(load_library().fam_step_static(ctypes.byref(cfg.to_c()), ctypes.c_void_p(stream_handle), _ptr(U),
+                                          float(t), float(dt_fixed), _ptr(dt_used), fp), "fam_step_static")
 
 
 def fam_set_time(h, t):

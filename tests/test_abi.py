@@ -43,7 +43,7 @@ def test_status_strings():
 
 
 def test_invalid_configurations_are_rejected_without_a_device():
-    from paper_2609_26194_amd.fam import FAM_ERR_ARG, FamConfig
+    from paper_2609_26194_amd.fam import FAM_ERR_ARG, FAM_ERR_SIZE, FamConfig
     lib = _lib()
     h = ctypes.c_void_p()
     for bad in (dict(dim=3, nx=8, ny=8), dict(dim=2, nx=8, ny=8, k=7), dict(dim=2, nx=2, ny=8),
@@ -67,6 +67,14 @@ def test_invalid_configurations_are_rejected_without_a_device():
     assert lib.fam_step(None, None, 0.0, None) == FAM_ERR_ARG
     assert lib.fam_run(None, None, 1.0, 0, 0.0, None, None) == FAM_ERR_ARG
     assert lib.fam_set_time(None, 0.0) == FAM_ERR_ARG
+    # the allocation-free step: argument checks and the size limit come before any device work
+    ok = FamConfig(dim=2, nx=64, ny=64, system="euler").to_c()
+    fake = ctypes.c_void_p(256)
+    assert lib.fam_step_static(None, None, fake, 0.0, 0.0, None, None) == FAM_ERR_ARG
+    assert lib.fam_step_static(ctypes.byref(ok), None, None, 0.0, 0.0, None, None) == FAM_ERR_ARG
+    assert lib.fam_step_static(ctypes.byref(ok), None, fake, float("nan"), 0.0, None, None) == FAM_ERR_ARG
+    big = FamConfig(dim=2, nx=600, ny=600, system="euler").to_c()    # 4.3e6 doubles: more than 64 MiB holds
+    assert lib.fam_step_static(ctypes.byref(big), None, fake, 0.0, 0.0, None, None) == FAM_ERR_SIZE
     assert lib.fam_dbg_recon(None, None, None) == FAM_ERR_ARG
     assert lib.fam_dbg_oe_factors(None, None, None, None) == FAM_ERR_ARG
 
