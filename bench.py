@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--adjoint-checkpoint", type=int, default=20, help="checkpoint spacing of the adjoint workload")
     p.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection run")
     p.add_argument("--dmr-t", type=float, default=0.2, help="final time of the double Mach reflection run")
+    p.add_argument("--dmr-cfl", type=float, default=0.55, help="CFL number of the double Mach reflection run "
+                   "(the paper's FAM5 discontinuous tests: 0.55)")
     p.add_argument("--no-char", action="store_true", help="skip the characteristic-variable comparison")
     p.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), help="record the HBM traffic of the stage kernel from two rocprofv3 counter CSVs")
     return p.parse_args()
@@ -150,36 +152,63 @@ def stored_traffic(key):
 # ---------------------------------------------------------------------------
 # measurements
 # ---------------------------------------------------------------------------
+def host_cpus():
+    """(threads to use, visible CPUs, CPU model): all CPUs this process may run on, capped by
+    OMP_NUM_THREADS when it is set (a host's share for one job)."""
+    visible = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = visible
+    cap = os.environ.get("OMP_NUM_THREADS")
+    threads = min(usable, int(cap)) if cap and cap.isdigit() and int(cap) > 0 else usable
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, visible, usable, model
+
+
 def cpu_baseline(n, steps):
-    """The oracle as it stands, on the same recipe at n x n for `steps` steps."""
+    """The oracle as it stands, on the same recipe at n x n for `steps` steps, with every host
+    thread this job may use, and on one thread for a smaller sample."""
     import torch
     import fam_inputs as fi
     from oracle.scheme import Config, step
-    threads = torch.get_num_threads()
+    threads, visible, usable, model = host_cpus()
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
     cfg = Config(dim=2, nx=n, ny=n, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
                  oe="type2", cfl=0.2, pp=True)
-    U = torch.tensor(fi.four_quadrant(n, 0))
-    U, _ = step(U, cfg)  # warm-up
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        U, _ = step(U, cfg)
-    dt = time.perf_counter() - t0
-    # the same oracle on one thread (a smaller sample of the same recipe)
-    n1, steps1 = 256, 2
-    cfg1 = Config(dim=2, nx=n1, ny=n1, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
-                  oe="type2", cfl=0.2, pp=True)
-    torch.set_num_threads(1)
     try:
+        U = torch.tensor(fi.four_quadrant(n, 0))
+        U, _ = step(U, cfg)  # warm-up
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            U, _ = step(U, cfg)
+        dt = time.perf_counter() - t0
+        # the same oracle on one thread (a smaller sample of the same recipe)
+        n1, steps1 = 256, 2
+        cfg1 = Config(dim=2, nx=n1, ny=n1, k=5, system="euler", bc_x="transmissive", bc_y="transmissive",
+                      oe="type2", cfl=0.2, pp=True)
+        torch.set_num_threads(1)
         V, _ = step(torch.tensor(fi.four_quadrant(n1, 0)), cfg1)  # warm-up
         t1 = time.perf_counter()
         for _ in range(steps1):
             V, _ = step(V, cfg1)
         dt1 = time.perf_counter() - t1
     finally:
-        torch.set_num_threads(threads)
+        torch.set_num_threads(prev)
     return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{n}x{n} cells of the same workload recipe, {steps} steps after one warm-up step "
                       f"({dt:.1f} s)",
+            "host": {"cpu_model": model, "nproc": visible, "usable_cpus": usable,
+                     "omp_num_threads": os.environ.get("OMP_NUM_THREADS")},
             "single_thread": {"value": n1 * n1 * steps1 / dt1, "cores": 1,
                               "sample": f"{n1}x{n1} cells, {steps1} steps after one warm-up step ({dt1:.1f} s)"}}
 
@@ -442,16 +471,17 @@ def char_leg(so_n=4000, so_steps=2000, dmr_steps=1000):
     return res
 
 
-def dmr_leg(t_final, nx=1440, ny=480):
+def dmr_leg(t_final, cfl, nx=1440, ny=480):
     """The paper's double Mach reflection run: [0, 3] x [0, 1], 1440 x 480, FAM5, OE Type II,
-    positivity limiter, CFL 0.2, to t_final; cell-updates/s and the split of one step's time
+    positivity limiter, to t_final at C = cfl (the paper's FAM5 discontinuous tests use 0.55,
+    Sec. 4, time stepping); cell-updates/s, the step count, and the split of one step's time
     between the three RK stage launches and the OE launch (HIP events on the library stream,
     at the final state)."""
     import torch
     import fam_inputs as fi
     from paper_2609_26194_amd import Fam, FamConfig
     cfg = FamConfig(dim=2, nx=nx, ny=ny, x0=0.0, x1=3.0, y0=0.0, y1=1.0, k=5, system="euler", oe="type2",
-                    cfl=0.2, pp=True, dmr=True)
+                    cfl=cfl, pp=True, dmr=True)
     U0 = torch.tensor(fi.double_mach(nx, ny), dtype=torch.float64).cuda()
     fam = Fam(cfg)
     tuned = fam.autotune(U0)
@@ -468,7 +498,8 @@ def dmr_leg(t_final, nx=1440, ny=480):
     tot = launch_split(fam, U)
     fam.close()
     return {"workload": f"double Mach reflection {nx}x{ny} on [0,3]x[0,1], FAM5, OE Type II, positivity limiter, "
-                        f"CFL 0.2, to t = {t:.4f}", "steps": steps, "cell_updates_per_s": nx * ny * steps / elapsed,
+                        f"CFL {cfl}, to t = {t:.4f}", "cfl": cfl, "steps": steps,
+            "cell_updates_per_s": nx * ny * steps / elapsed,
             "ms_per_step": elapsed / steps * 1e3, "seconds": elapsed,
             # standalone launches of one step (each stage launch re-cuts its segment list; inside the
             # graph-replayed step that happens once), and the OE's share of them
@@ -550,7 +581,7 @@ def main():
         out["batched"] = batched(args.batched_steps)
     if not args.no_dmr:
         log("double Mach reflection")
-        out["dmr"] = dmr_leg(args.dmr_t)
+        out["dmr"] = dmr_leg(args.dmr_t, args.dmr_cfl)
     if not args.no_char:
         log("characteristic variables")
         out["characteristic_variables"] = char_leg()
