@@ -396,7 +396,7 @@ static fam_status init_segments(fam_ctx* c) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     return FAM_ERR_DEVICE;
   const int strips = (f.nx + fam::STRIP - 1) / fam::STRIP;
-  c->seg_budget = 4 * cus;   // one stage wave per SIMD
+  c->seg_budget = 4 * FAM_STAGE_WAVES * cus;   // every stage wave slot of the chip
   if (strips > c->seg_budget || strips > fam::PART_MAX_STRIPS) {
     c->seg_budget = 0;
     return FAM_OK;

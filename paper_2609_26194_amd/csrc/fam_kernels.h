@@ -10,6 +10,10 @@
 namespace fam {
 
 constexpr int STRIP = 60;   // output columns per 2D strip (one wavefront)
+// waves of the RK stage kernel per SIMD that its register and LDS budget allows
+#ifndef FAM_STAGE_WAVES
+#define FAM_STAGE_WAVES 1
+#endif
 
 struct PhysParams {
   double gamma, ax, ay;

@@ -39,9 +39,6 @@
 
 namespace fam {
 
-#ifndef FAM_STAGE_WAVES
-#define FAM_STAGE_WAVES 1
-#endif
 #ifndef FAM_OE_WAVES
 #define FAM_OE_WAVES 1
 #endif
@@ -98,7 +95,10 @@ __device__ __forceinline__ double half_wave_min(double v) {
 }
 
 // LDS staging of the limiter's exact test: up to 8 cells of a wave at a time
-constexpr int PP_CHUNK = 8;
+#ifndef FAM_PP_CHUNK
+#define FAM_PP_CHUNK 8
+#endif
+constexpr int PP_CHUNK = FAM_PP_CHUNK;
 struct PPStage {
   double cf[PP_CHUNK][4 * 21 + 1];   // coefficients of the 4 components, eps
   double th[PP_CHUNK][2];
@@ -562,6 +562,10 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     store_row<NPLU>(W, slot_of(r), lane, reg);
   }
   __syncthreads();
+  // rows are fetched two iterations ahead of their store into the window: ra holds
+  // row r + 2 during iteration r, rb receives row r + 3
+  double ra[NPLU], rb[NPLU];
+  if (j0 + 1 <= rend + 1) fetch_row<NPLU, DMR>(Un, in, i0, j0 + 1, lane, ra, tb);
 
   double prevTopC[NC];     // face-centre value at the top of the row below
   double prevJb[NC];       // |jump| at the bottom face of the row below
@@ -585,7 +589,8 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
 #pragma unroll 1
   for (int r = j0 - 1; r <= rend; ++r) {
     const bool pre = (r + 2 <= rend + 1);
-    if (pre) fetch_row<NPLU, DMR>(Un, in, i0, r + 2, lane, reg, tb);
+    const bool pre2 = (r + 3 <= rend + 1);
+    if (pre2) fetch_row<NPLU, DMR>(Un, in, i0, r + 3, lane, rb, tb);
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1);
 
@@ -601,8 +606,9 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
       {
         const double Jy = prevJb[c] + Jb;
         if (!(pD[c] < pEps[c])) {
-          sx = fmax(sx, A.gamma_k * pJx[c] / pD[c]);
-          sy = fmax(sy, A.gamma_k * Jy / pD[c]);
+          const double gD = A.gamma_k / pD[c];
+          sx = fmax(sx, gD * pJx[c]);
+          sy = fmax(sy, gD * Jy);
         }
       }
       if (r < rend) {
@@ -670,8 +676,10 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
     spy[1] = spy[2];
 
     __syncthreads();
-    if (pre) store_row<NPLU>(W, slot_of(r + 2), lane, reg);
+    if (pre) store_row<NPLU>(W, slot_of(r + 2), lane, ra);
     __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NPLU; ++p) ra[p] = rb[p];
   }
   __syncthreads();
 }
