@@ -19,10 +19,11 @@
 //      reconstruction (compile-time weights) applied to n's coefficient adjoint.
 //  (3) alpha route: dJ/dalpha times the gradient of the spectral radius at the
 //      cell average that attains the maximum (first index on ties).
-// OE^T (Type II) in three gather passes: per cell, the derivative of the damping
+// OE^T (Type II) in two LDS-tiled passes: per cell, the derivative of the damping
 // factor with respect to the jump sums, the denominators and the wave-speed
-// bounds; per face, the jump adjoints; per cell, the transposed face-centre
-// functionals and the denominator / wave-speed routes over the 3x3 patch.
+// bounds; then per cell, the face adjoints of its 3x3 neighbours, gathered
+// through the transposed face-centre functionals, and the denominator /
+// wave-speed routes over the 3x3 patch.
 // Non-smooth points: |x|' = sign(x) with sign(0) = 0; maxima pass the derivative
 // to the first maximal entry; the zero-denominator branch has zero derivative.
 //
@@ -617,86 +618,127 @@ __global__ void __launch_bounds__(RED_T) adj_alpha_route_kernel(AdjMesh m, const
 // ---------------------------------------------------------------------------
 // OE adjoint (Type II)
 // ---------------------------------------------------------------------------
-// pre-pass record per cell (CS planes): [4c + f] face-centre value f (r, l, t, b)
-// of component c, 16, 17: spectral radii in x and y at the cell average.
-constexpr int CS = 18;
 // per-cell record (OES planes): [0..3] jump at the left face, [4..7] jump at the
-// bottom face, [8..11] dJ/dJx, [12..15] dJ/dJy (read by the face pass);
-// [16..19] dJ/dD * sign(u_p* - S), 20 packed patch indices (p* of the four
-// components, argmax beta_x, argmax beta_y; 4 bits each), 21, 22 dJ/dbeta_x, y
-// (read by the gather pass).
+// bottom face, [8..11] dJ/dJx, [12..15] dJ/dJy (read for the face-centre
+// adjoints); [16..19] dJ/dD * sign(u_p* - S), 20 packed patch indices (p* of the
+// four components, argmax beta_x, argmax beta_y; 4 bits each), 21, 22 dJ/dbeta_x, y
+// (read by the gather).
 constexpr int OES = 23;
 
+// ---------------------------------------------------------------------------
+// OE adjoint in two LDS-tiled passes:
+//  rec:    per block, the face-centre values, averages and spectral radii of its
+//          cells and a one-cell ring (from a 20 x 20 tile of Un, one component at a
+//          time); then per cell the damping factor, lamN = delta lam (first moments),
+//          and the record: the derivative of delta with respect to the jump sums,
+//          the denominators (routed to the patch cell attaining the maximum) and
+//          the wave-speed bounds (first maximal entry);
+//  gather: per block and component, the face-centre adjoints of its cells and a
+//          one-cell ring (from a 20 x 20 tile of the record's jumps and jump-sum
+//          adjoints), gathered through the transposed face-centre functionals, then
+//          the denominator and wave-speed routes.
+// ---------------------------------------------------------------------------
+constexpr int FG = ADJ_TX + 4, FGC = FG * FG;        // a block's cells and a two-cell ring
+constexpr int FNLP = (FGC + ADJ_T - 1) / ADJ_T;
+static_assert(ADJ_TX == ADJ_TY, "square blocks");
+
 template <int K>
-__global__ void __launch_bounds__(ADJ_T) oe_adj_pre_kernel(AdjMesh m, const double* __restrict__ Un,
-                                                           double* __restrict__ cs) {
+__global__ void __launch_bounds__(ADJ_T) oe_adj_rec_kernel(AdjMesh m, const double* __restrict__ Un,
+                                                           const double* __restrict__ lam, double dt, double gk,
+                                                           double* __restrict__ lamN, double* __restrict__ os) {
+  __shared__ double st[3][FGC];    // one component's three planes over the 20 x 20 region
+  __shared__ double cv[16][GTC];   // face-centre values [4c + f] (f: r, l, t, b) over the 18 x 18 region
+  __shared__ double av[4][GTC];    // averages over the 18 x 18 region
+  __shared__ double sp[2][GTC];    // spectral radii in x and y over the 18 x 18 region
+  const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
   const int2 bt = block_tile();
-  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
-  if (i >= m.nx || j >= m.ny) return;
-  const Patch P = patch_of(m, i, j);
-  const size_t id = P.id(4);
-  using Seq = std::make_integer_sequence<int, 27>;
+  const int i0 = bt.x * ADJ_TX, j0 = bt.y * ADJ_TY;
+  const int i = i0 + tx, j = j0 + ty;
+  size_t src[FNLP];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double u0[9], u1[9], u2[9];
-    gstencil<K>(Un, m, c, P, u0, u1, u2);
-    double u[27];
-#pragma unroll
-    for (int l = 0; l < 9; ++l) {
-      u[l] = u0[l];
-      u[9 + l] = u1[l];
-      u[18 + l] = u2[l];
-    }
-    cs[(size_t)(4 * c + 0) * m.plane + id] = centre_dot<K, false, 0>(u, Seq{});
-    cs[(size_t)(4 * c + 1) * m.plane + id] = centre_dot<K, false, 1>(u, Seq{});
-    cs[(size_t)(4 * c + 2) * m.plane + id] = centre_dot<K, false, 2>(u, Seq{});
-    cs[(size_t)(4 * c + 3) * m.plane + id] = centre_dot<K, false, 3>(u, Seq{});
+  for (int t = 0; t < FNLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+    const int py = p / FG, px = p - py * FG;
+    src[t] = p < FGC ? wrap_idx(m, i0 - 2 + px, j0 - 2 + py) : 0;
   }
+  using Seq = std::make_integer_sequence<int, 27>;
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < FNLP; ++t) {
+      const int p = threadIdx.x + t * ADJ_T;
+      if (p < FGC) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) st[q][p] = Un[(size_t)(c * 3 + q) * m.plane + src[t]];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NLP; ++t) {
+      const int p = threadIdx.x + t * ADJ_T;
+      if (p < GTC) {
+        const int py = p / GT, px = p - py * GT;   // region (px, py) = tile (px + 1, py + 1)
+        double u[27];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int l = b * 3 + a, f = (py + b) * FG + (px + a);
+            u[l] = st[0][f];
+            u[9 + l] = slot_used<K>(9 + l) ? st[1][f] : 0.0;
+            u[18 + l] = slot_used<K>(18 + l) ? st[2][f] : 0.0;
+          }
+        cv[4 * c + 0][p] = centre_dot<K, false, 0>(u, Seq{});
+        cv[4 * c + 1][p] = centre_dot<K, false, 1>(u, Seq{});
+        cv[4 * c + 2][p] = centre_dot<K, false, 2>(u, Seq{});
+        cv[4 * c + 3][p] = centre_dot<K, false, 3>(u, Seq{});
+        av[c][p] = u[4];
+      }
+    }
+  }
+  __syncthreads();
   const Euler<2> ph{m.gamma};
   bool bad = false;
-  double a[4] = {Un[id], Un[3 * m.plane + id], Un[6 * m.plane + id], Un[9 * m.plane + id]};
-  cs[(size_t)16 * m.plane + id] = ph.speed(0, a, bad);
-  cs[(size_t)17 * m.plane + id] = ph.speed(1, a, bad);
-}
-
-__global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double* __restrict__ Un,
-                                                         const double* __restrict__ cs,
-                                                         const double* __restrict__ lam, double dt, double gk,
-                                                         double* __restrict__ lamN, double* __restrict__ os) {
-  const int2 bt = block_tile();
-  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
+#pragma unroll
+  for (int t = 0; t < NLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+    if (p < GTC) {
+      const double a[4] = {av[0][p], av[1][p], av[2][p], av[3][p]};
+      sp[0][p] = ph.speed(0, a, bad);
+      sp[1][p] = ph.speed(1, a, bad);
+    }
+  }
+  __syncthreads();
   if (i >= m.nx || j >= m.ny) return;
-  const Patch P = patch_of(m, i, j);
-  const size_t id = P.id(4), il = P.id(3), ir = P.id(5), ib = P.id(1), it = P.id(7);
+  const int rp = (ty + 1) * GT + (tx + 1);   // this cell in the region
+  const size_t id = (size_t)j * m.nx + i;
   double Jx[4], Jy[4], jL[4], jB[4], D[4], eps[4], sD[4];
   int pD[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const double* C = cs + (size_t)(4 * c) * m.plane;
-    jL[c] = C[m.plane + id] - C[il];                              // l(i) - r(i-1)
-    const double jR = C[m.plane + ir] - C[id];                    // l(i+1) - r(i)
-    jB[c] = C[3 * m.plane + id] - C[2 * m.plane + ib];            // b(j) - t(j-1)
-    const double jT = C[3 * m.plane + it] - C[2 * m.plane + id];  // b(j+1) - t(j)
+    jL[c] = cv[4 * c + 1][rp] - cv[4 * c + 0][rp - 1];            // l(i) - r(i-1)
+    const double jR = cv[4 * c + 1][rp + 1] - cv[4 * c + 0][rp];   // l(i+1) - r(i)
+    jB[c] = cv[4 * c + 3][rp] - cv[4 * c + 2][rp - GT];            // b(j) - t(j-1)
+    const double jT = cv[4 * c + 3][rp + GT] - cv[4 * c + 2][rp];  // b(j+1) - t(j)
     Jx[c] = fabs(jL[c]) + fabs(jR);
     Jy[c] = fabs(jB[c]) + fabs(jT);
     double v[9];
     double S = 0.0, mabs = 0.0;
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      v[p] = Un[(c * 3) * m.plane + P.id(p)];
-      S += v[p];
-      mabs = fmax(mabs, fabs(v[p]));
+    for (int q = 0; q < 9; ++q) {
+      v[q] = av[c][rp + (q / 3 - 1) * GT + (q % 3 - 1)];
+      S += v[q];
+      mabs = fmax(mabs, fabs(v[q]));
     }
     double best = -1.0;
     int arg = 0;
 #pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      const double d = fabs(v[p] - S);
+    for (int q = 0; q < 9; ++q) {
+      const double d = fabs(v[q] - S);
       if (d > best) {
         best = d;
-        arg = p;
+        arg = q;
       }
     }
     D[c] = best;
@@ -704,16 +746,15 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
     sD[c] = sgn(v[arg] - S);
     eps[c] = 1e-14 * fmax(mabs, 1.0);
   }
-  // wave-speed bounds over the patch (first maximal entry)
   double bx = -1.0, by = -1.0;
   int abx = 0, aby = 0;
 #pragma unroll
-  for (int p = 0; p < 9; ++p) {
-    const double sx = cs[(size_t)16 * m.plane + P.id(p)], sy = cs[(size_t)17 * m.plane + P.id(p)];
-    if (sx > bx) { bx = sx; abx = p; }
-    if (sy > by) { by = sy; aby = p; }
+  for (int q = 0; q < 9; ++q) {
+    const int pos = rp + (q / 3 - 1) * GT + (q % 3 - 1);
+    const double sx = sp[0][pos], sy = sp[1][pos];
+    if (sx > bx) { bx = sx; abx = q; }
+    if (sy > by) { by = sy; aby = q; }
   }
-  // sigma per component and its maximum (first maximal component)
   double sgx = -1.0, sgy = -1.0;
   int cx = 0, cy = 0;
 #pragma unroll
@@ -740,7 +781,6 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
   const double bbx = tbar * kx * sgx, bby = tbar * ky * sgy;
   const double sbx = tbar * kx * bx, sby = tbar * ky * by;
   double Jxb[4] = {0, 0, 0, 0}, Jyb[4] = {0, 0, 0, 0}, Db[4] = {0, 0, 0, 0};
-  // (the small-denominator branch has zero derivative)
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (c == cx && !(D[c] < eps[c])) {
@@ -766,104 +806,117 @@ __global__ void __launch_bounds__(ADJ_T) oe_adj_a_kernel(AdjMesh m, const double
   os[(size_t)22 * m.plane + id] = bby;
 }
 
-// face-centre value adjoints of every cell: [c][r, l, t, b]
-__global__ void __launch_bounds__(ADJ_T) oe_adj_b_kernel(AdjMesh m, const double* __restrict__ os,
-                                                         double* __restrict__ cb) {
-  const int2 bt = block_tile();
-  const int i = bt.x * ADJ_TX + (threadIdx.x % ADJ_TX);
-  const int j = bt.y * ADJ_TY + (threadIdx.x / ADJ_TX);
-  if (i >= m.nx || j >= m.ny) return;
-  const size_t id = (size_t)j * m.nx + i;
-  const size_t il = (size_t)j * m.nx + wrap_near(i - 1, m.nx), ir = (size_t)j * m.nx + wrap_near(i + 1, m.nx);
-  const size_t ib = (size_t)wrap_near(j - 1, m.ny) * m.nx + i, it = (size_t)wrap_near(j + 1, m.ny) * m.nx + i;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double jL = os[(size_t)c * m.plane + id], jR = os[(size_t)c * m.plane + ir];
-    const double jB = os[(size_t)(4 + c) * m.plane + id], jT = os[(size_t)(4 + c) * m.plane + it];
-    const double Jxq = os[(size_t)(8 + c) * m.plane + id];
-    const double Jyq = os[(size_t)(12 + c) * m.plane + id];
-    const double bL = sgn(jL) * (Jxq + os[(size_t)(8 + c) * m.plane + il]);
-    const double bR = sgn(jR) * (Jxq + os[(size_t)(8 + c) * m.plane + ir]);
-    const double bB = sgn(jB) * (Jyq + os[(size_t)(12 + c) * m.plane + ib]);
-    const double bT = sgn(jT) * (Jyq + os[(size_t)(12 + c) * m.plane + it]);
-    cb[(size_t)(c * 4 + 0) * m.plane + id] = -bR;
-    cb[(size_t)(c * 4 + 1) * m.plane + id] = bL;
-    cb[(size_t)(c * 4 + 2) * m.plane + id] = -bT;
-    cb[(size_t)(c * 4 + 3) * m.plane + id] = bB;
-  }
-}
-
-// gather over the 3x3 neighbours n of each cell q, from an LDS tile of the
-// block's cells and a one-cell ring: the transposed face-centre functionals of
-// n's centre adjoints, and the denominator (-s to every patch cell, +s to p*)
-// and wave-speed (gradient at the argmax cell) routes.
-constexpr int OE_TILE_PLANES = 16 + 4 + 3;   // cb, dJ/dD * s, packed indices + beta adjoints
-
 template <int K>
-__global__ void __launch_bounds__(ADJ_T) oe_adj_c_kernel(AdjMesh m, const double* __restrict__ Un,
-                                                         const double* __restrict__ os,
-                                                         const double* __restrict__ cb, double* __restrict__ lamN) {
-  __shared__ double sh[OE_TILE_PLANES][GTC];
+__global__ void __launch_bounds__(ADJ_T) oe_adj_gather_kernel(AdjMesh m, const double* __restrict__ Un,
+                                                              const double* __restrict__ os,
+                                                              double* __restrict__ lamN) {
+  __shared__ double t4[4][FGC];    // one component's jL, jB, dJ/dJx, dJ/dJy over the 20 x 20 region
+  __shared__ double cbt[4][GTC];   // its face-centre adjoints (r, l, t, b) over the 18 x 18 region
+  __shared__ double ex[7][GTC];    // dJ/dD * s (4 components), packed indices, beta adjoints over 18 x 18
   const int tx = threadIdx.x % ADJ_TX, ty = threadIdx.x / ADJ_TX;
   const int2 bt = block_tile();
   const int i0 = bt.x * ADJ_TX, j0 = bt.y * ADJ_TY;
   const int i = i0 + tx, j = j0 + ty;
-  constexpr int NLP = (GTC + ADJ_T - 1) / ADJ_T;
+  const bool inside = i < m.nx && j < m.ny;
+  size_t src[FNLP];
+#pragma unroll
+  for (int t = 0; t < FNLP; ++t) {
+    const int p = threadIdx.x + t * ADJ_T;
+    const int py = p / FG, px = p - py * FG;
+    src[t] = p < FGC ? wrap_idx(m, i0 - 2 + px, j0 - 2 + py) : 0;
+  }
 #pragma unroll
   for (int t = 0; t < NLP; ++t) {
     const int p = threadIdx.x + t * ADJ_T;
     if (p < GTC) {
       const int py = p / GT, px = p - py * GT;
-      const size_t src = wrap_idx(m, i0 - 1 + px, j0 - 1 + py);
+      const size_t sr = wrap_idx(m, i0 - 1 + px, j0 - 1 + py);
 #pragma unroll
-      for (int pl = 0; pl < 16; ++pl) sh[pl][p] = cb[(size_t)pl * m.plane + src];
-#pragma unroll
-      for (int pl = 16; pl < OE_TILE_PLANES; ++pl) sh[pl][p] = os[(size_t)pl * m.plane + src];
+      for (int q = 0; q < 7; ++q) ex[q][p] = os[(size_t)(16 + q) * m.plane + sr];
     }
   }
-  __syncthreads();
-  if (i >= m.nx || j >= m.ny) return;
-  const size_t id = (size_t)j * m.nx + i;
-  double avg[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) avg[c] = Un[(c * 3) * m.plane + id];
   double acc[4][3] = {};
-  double gx[4], gy[4];
-  speed_grad(0, m.gamma, avg, gx);
-  speed_grad(1, m.gamma, avg, gy);
 #pragma unroll 1
-  for (int dy = -1; dy <= 1; ++dy)
+  for (int c = 0; c < 4; ++c) {
+    __syncthreads();
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int pos = (ty + 1 + dy) * GT + (tx + 1 + dx);
-      const int L9 = (1 - dx) + 3 * (1 - dy);   // position of q in the patch of n = q + (dx, dy)
-      const int packed = (int)sh[20][pos];
+    for (int t = 0; t < FNLP; ++t) {
+      const int p = threadIdx.x + t * ADJ_T;
+      if (p < FGC) {
+        t4[0][p] = os[(size_t)c * m.plane + src[t]];
+        t4[1][p] = os[(size_t)(4 + c) * m.plane + src[t]];
+        t4[2][p] = os[(size_t)(8 + c) * m.plane + src[t]];
+        t4[3][p] = os[(size_t)(12 + c) * m.plane + src[t]];
+      }
+    }
+    __syncthreads();
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double b[4];
+    for (int t = 0; t < NLP; ++t) {
+      const int p = threadIdx.x + t * ADJ_T;
+      if (p < GTC) {
+        const int py = p / GT, px = p - py * GT;
+        const int f = (py + 1) * FG + (px + 1);   // the same cell in the 20 x 20 tile
+        const double jLv = t4[0][f], jRv = t4[0][f + 1], jBv = t4[1][f], jTv = t4[1][f + FG];
+        const double Jxq = t4[2][f], Jyq = t4[3][f];
+        const double bL = sgn(jLv) * (Jxq + t4[2][f - 1]);
+        const double bR = sgn(jRv) * (Jxq + t4[2][f + 1]);
+        const double bB = sgn(jBv) * (Jyq + t4[3][f - FG]);
+        const double bT = sgn(jTv) * (Jyq + t4[3][f + FG]);
+        cbt[0][p] = -bR;
+        cbt[1][p] = bL;
+        cbt[2][p] = -bT;
+        cbt[3][p] = bB;
+      }
+    }
+    __syncthreads();
+    if (inside) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) b[f] = sh[4 * c + f][pos];
-        switch (L9) {
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int pos = (ty + 1 + dy) * GT + (tx + 1 + dx);
+          const int L9 = (1 - dx) + 3 * (1 - dy);   // position of q in the patch of n = q + (dx, dy)
+          double b[4];
+#pragma unroll
+          for (int f = 0; f < 4; ++f) b[f] = cbt[f][pos];
+          switch (L9) {
 #define FAM_CW3(P)                                    \
   case P:                                             \
     acc[c][0] += cwt_dot<K, false, P>(b);             \
     acc[c][1] += cwt_dot<K, false, 9 + P>(b);         \
     acc[c][2] += cwt_dot<K, false, 18 + P>(b);        \
     break;
-          FAM_CW3(0) FAM_CW3(1) FAM_CW3(2) FAM_CW3(3) FAM_CW3(4) FAM_CW3(5) FAM_CW3(6) FAM_CW3(7) FAM_CW3(8)
+            FAM_CW3(0) FAM_CW3(1) FAM_CW3(2) FAM_CW3(3) FAM_CW3(4) FAM_CW3(5) FAM_CW3(6) FAM_CW3(7) FAM_CW3(8)
 #undef FAM_CW3
+          }
+          const int packed = (int)ex[4][pos];
+          const int ps = (packed >> (4 * c)) & 15;
+          acc[c][0] += ps == L9 ? 0.0 : -ex[c][pos];
         }
-        const double ds = sh[16 + c][pos];
-        const int ps = (packed >> (4 * c)) & 15;
-        acc[c][0] += ps == L9 ? 0.0 : -ds;
-      }
+    }
+  }
+  if (!inside) return;
+  const size_t id = (size_t)j * m.nx + i;
+  double avg[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) avg[c] = Un[(c * 3) * m.plane + id];
+  double gx[4], gy[4];
+  speed_grad(0, m.gamma, avg, gx);
+  speed_grad(1, m.gamma, avg, gy);
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int pos = (ty + 1 + dy) * GT + (tx + 1 + dx);
+      const int L9 = (1 - dx) + 3 * (1 - dy);
+      const int packed = (int)ex[4][pos];
       if (((packed >> 16) & 15) == L9) {
-        const double bb = sh[21][pos];
+        const double bb = ex[5][pos];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c][0] += bb * gx[c];
       }
       if (((packed >> 20) & 15) == L9) {
-        const double bb = sh[22][pos];
+        const double bb = ex[6][pos];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c][0] += bb * gy[c];
       }
@@ -935,9 +988,7 @@ struct FamAdjointScratch {
   double* lam2 = nullptr;
   double* lam0 = nullptr;
   double* abar = nullptr;     // coefficient adjoints [4][NCF][cells]
-  double* os = nullptr;       // OE record [32][cells]
-  double* cb = nullptr;       // face-centre adjoints [4][4][cells]
-  double* cs = nullptr;       // OE pre-pass: face-centre values and wave speeds [18][cells]
+  double* os = nullptr;       // OE record [OES][cells]
   double* partial = nullptr;  // per-block alpha adjoints / functional sums
   double* smax = nullptr;     // alpha_x, alpha_y
   double* Jd = nullptr;
@@ -950,7 +1001,7 @@ void fam_adjoint_free(fam_ctx* c) {
   if (!c || !c->adj) return;
   FamAdjointScratch* s = c->adj;
   void* bufs[] = {s->ckpt, s->segbuf, s->ucur, s->lam, s->lamN, s->lam1, s->lam2, s->lam0, s->abar,
-                  s->os, s->cb, s->cs, s->partial, s->smax, s->Jd, s->apv, s->sidx, s->api};
+                  s->os, s->partial, s->smax, s->Jd, s->apv, s->sidx, s->api};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete s;
@@ -978,8 +1029,7 @@ static fam_status adj_alloc(fam_ctx* c, int ncp, int seg) {
   } al[] = {{(void**)&s->ckpt, L * ncp}, {(void**)&s->segbuf, L * 4 * seg}, {(void**)&s->ucur, L},
             {(void**)&s->lam, L}, {(void**)&s->lamN, L}, {(void**)&s->lam1, L}, {(void**)&s->lam2, L},
             {(void**)&s->lam0, L}, {(void**)&s->abar, D * 4 * 21 * s->cells},
-            {(void**)&s->os, D * fam::OES * s->cells}, {(void**)&s->cb, D * 16 * s->cells},
-            {(void**)&s->cs, D * fam::CS * s->cells},
+            {(void**)&s->os, D * fam::OES * s->cells},
             {(void**)&s->partial, D * 2 * nb}, {(void**)&s->smax, D * 2}, {(void**)&s->Jd, D},
             {(void**)&s->apv, D * 2 * fam::ALPHA_BLOCKS}, {(void**)&s->sidx, sizeof(int) * 2},
             {(void**)&s->api, sizeof(int) * 2 * fam::ALPHA_BLOCKS}};
@@ -1014,11 +1064,9 @@ static void oe_T_apply(fam_ctx* c, const fam::AdjMesh& m, const double* Un, cons
                        double* lamN, hipStream_t st) {
   FamAdjointScratch* s = c->adj;
   const dim3 grid((m.nx + fam::ADJ_TX - 1) / fam::ADJ_TX, (m.ny + fam::ADJ_TY - 1) / fam::ADJ_TY);
-  hipLaunchKernelGGL((fam::oe_adj_pre_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, s->cs);
-  hipLaunchKernelGGL(fam::oe_adj_a_kernel, grid, dim3(fam::ADJ_T), 0, st, m, Un, s->cs, lam, dt, c->gamma_k,
+  hipLaunchKernelGGL((fam::oe_adj_rec_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, lam, dt, c->gamma_k,
                      lamN, s->os);
-  hipLaunchKernelGGL(fam::oe_adj_b_kernel, grid, dim3(fam::ADJ_T), 0, st, m, s->os, s->cb);
-  hipLaunchKernelGGL((fam::oe_adj_c_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, s->os, s->cb, lamN);
+  hipLaunchKernelGGL((fam::oe_adj_gather_kernel<K>), grid, dim3(fam::ADJ_T), 0, st, m, Un, s->os, lamN);
 }
 
 template <int K>
