@@ -245,9 +245,26 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
 // ---------------------------------------------------------------------------
 // stage tile
 // ---------------------------------------------------------------------------
+// The values a row hands to the next (its top traces, the bottom states of the
+// next y-face, and its residual without the top face) stay in registers, except
+// for the Euler equations at k = 6, whose 4 x 21 coefficients leave no room for
+// them: there each lane keeps its own column of them in LDS.
+template <int K, int NC>
+__host__ __device__ constexpr bool carry_in_lds() { return K == 6 && NC == 4; }
+
+template <bool ON>
+struct StageCarry {
+  double top[16][LANES];    // [component * 4 + point][lane]
+  double part[NPL][LANES];  // [component * 3 + moment][lane]
+};
+template <>
+struct StageCarry<false> {
+  char unused;
+};
 template <int K, class P, bool PP, bool DMR = false, bool CHAR = false>
 __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, int i0, int j0, int H,
-                           Window& W, PPStage& PS, double& amax_x, double& amax_y, bool& bad) {
+                           Window& W, PPStage& PS, StageCarry<carry_in_lds<K, P::NC>()>& T, double& amax_x,
+                           double& amax_y, bool& bad) {
   constexpr int NC = P::NC;
   constexpr int NCF = ncoef2d(K);
   constexpr int MD = maxdeg(K);
@@ -275,14 +292,23 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   }
   __syncthreads();
 
-  double prevTop[NC][4];     // top trace of the row below (face j-1/2 of the current row)
-  double part[NC][3];        // residual of the row below without its top face
+  constexpr bool CL = carry_in_lds<K, NC>();
+  double topR[CL ? 1 : NC][4];    // top trace of the row below (face j-1/2 of the current row)
+  double partR[CL ? 1 : NC][3];   // residual of the row below without its top face
+  auto prevTop = [&](int c, int q) -> double& {
+    if constexpr (CL) return T.top[c * 4 + q][col];
+    else return topR[c][q];
+  };
+  auto part = [&](int c, int m) -> double& {
+    if constexpr (CL) return T.part[c * 3 + m][col];
+    else return partR[c][m];
+  };
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) prevTop[c][q] = 0.0;
+    for (int q = 0; q < 4; ++q) prevTop(c, q) = 0.0;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) part[c][m] = 0.0;
+    for (int m = 0; m < 3; ++m) part(c, m) = 0.0;
   }
 
 #pragma unroll 1
@@ -384,7 +410,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
         for (int q = 0; q < 4; ++q) {
           double ul[NC], ur[NC], fl[NC], fr[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) { ul[c] = prevTop[c][q]; ur[c] = bt[c][q]; }
+          for (int c = 0; c < NC; ++c) { ul[c] = prevTop(c, q); ur[c] = bt[c][q]; }
           phys.flux(1, ul, fl);
           phys.flux(1, ur, fr);
 #pragma unroll
@@ -403,7 +429,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       double avg[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const double Rm[3] = {part[c][0] - Gb[c] * idy, part[c][1] - Gt[c] * idy, part[c][2] - Gb[c] * i2dy};
+        const double Rm[3] = {part(c, 0) - Gb[c] * idy, part(c, 1) - Gt[c] * idy, part(c, 2) - Gb[c] * i2dy};
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const double L = W.v[sl][c * 3 + m][col] + dt * Rm[m];
@@ -423,7 +449,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       double E[MD + 1][4], O[MD + 1][3];
       contract_y<NCF, MD>(cf[c], E, O);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) prevTop[c][q] = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
+      for (int q = 0; q < 4; ++q) prevTop(c, q) = eval_pt<MD>(E, O, qnode(q), qsign(q), 2, 1.0);
     }
 
     if (!ring_lo) {
@@ -495,9 +521,9 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        part[c][0] = -(FbR[c] - Fb[c]) * idx_ + Gb[c] * idy;
-        part[c][1] = V1[c] * idx_ - (FbR[c] + Fb[c]) * i2dx + Gt[c] * idy;
-        part[c][2] = V2[c] * idy - Gb[c] * i2dy - (FtR[c] - Ft[c]) * idx_;
+        part(c, 0) = -(FbR[c] - Fb[c]) * idx_ + Gb[c] * idy;
+        part(c, 1) = V1[c] * idx_ - (FbR[c] + Fb[c]) * i2dx + Gt[c] * idy;
+        part(c, 2) = V2[c] * idy - Gb[c] * i2dy - (FtR[c] - Ft[c]) * idx_;
       }
     }
 
@@ -737,6 +763,7 @@ template <int K, class P, bool PP, bool DMR, bool CHAR = false>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
   __shared__ PPStage PS;
+  __shared__ StageCarry<carry_in_lds<K, P::NC>()> T;
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
   double amx = 0.0, amy = 0.0;
@@ -757,7 +784,7 @@ __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
     i0 = (T % gridDim.x) * STRIP;
     j0 = (T / gridDim.x) * H;
   }
-  stage_tile<K, P, PP, DMR, CHAR>(phys, A, in, i0, j0, H, W, PS, amx, amy, bad);
+  stage_tile<K, P, PP, DMR, CHAR>(phys, A, in, i0, j0, H, W, PS, T, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
   if constexpr (PP) {
     if (threadIdx.x == 0) A.tile_work[tile] = PS.nwork;
@@ -807,6 +834,7 @@ __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const i
                                                     const int* __restrict__ nseg) {
   __shared__ Window W;
   __shared__ PPStage PS;
+  __shared__ StageCarry<carry_in_lds<K, P::NC>()> T;
   if (*A.done) return;
   const int n = *nseg;
   if ((int)blockIdx.x >= n) return;
@@ -817,7 +845,7 @@ __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const i
   double amx = 0.0, amy = 0.0;
   bool bad = false;
   PS.nwork = 0;
-  stage_tile<K, P, true, DMR, CHAR>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
+  stage_tile<K, P, true, DMR, CHAR>(phys, A, in, it.y, it.z, it.w, W, PS, T, amx, amy, bad);
   flush_wave_results(amx, amy, bad, in.alpha_out, A.flag);
 }
 
@@ -991,6 +1019,7 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
                                                                 const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
   __shared__ PPStage PS;
+  __shared__ StageCarry<carry_in_lds<K, P::NC>()> T;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
   // one item per workgroup: the XCD-aware order (limiter on: heavy items first)
@@ -1006,7 +1035,7 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
     if (in.done && *in.done) continue;
     double amx = 0.0, amy = 0.0;
     if constexpr (PP) PS.nwork = 0;
-    stage_tile<K, P, PP>(phys, A, in, it.y, it.z, it.w, W, PS, amx, amy, bad);
+    stage_tile<K, P, PP>(phys, A, in, it.y, it.z, it.w, W, PS, T, amx, amy, bad);
     flush_wave_results(amx, amy, false, in.alpha_out, A.flag);
     if constexpr (PP) {
       if (threadIdx.x == 0) A.tile_work[wi] = PS.nwork;
