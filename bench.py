@@ -242,8 +242,8 @@ def stage_roofline(fam, U, k, cells, seg_list, reps=10):
     key = f"stage2d_list_kernel<{k}" if seg_list else f"stage2d_kernel<{k}"
     traffic = stored_traffic(key)
     if seg_list:
-        kernel = (f"stage2d_list_kernel<{k}, Euler<2>> and the partition of the next launch's segments "
-                  f"(part_scan_kernel, part_cut_kernel) (mean of the three RK stage launches)")
+        kernel = (f"stage2d_list_kernel<{k}, Euler<2>> (mean of the three RK stage launches; as in a step, "
+                  f"the stage-0 launch also re-cuts the segment list: part_scan_kernel, part_cut_kernel)")
     else:
         kernel = (f"stage2d_kernel<{k}, Euler<2>, true> and its tile_order_kernel (mean of the three RK "
                   f"stage launches)")

@@ -165,7 +165,9 @@ fam_status fam_set_time(fam_ctx* ctx, double t);
  *            the wave-speed reduction used by the next fam_stage(s = 0).
  * fam_stage: Uout = a_s U0 + b_s (Us + dt R(Us)) with (a_s, b_s) = (0, 1),
  *            (3/4, 1/4), (1/3, 2/3) for s = 0, 1, 2 (eq. 12).  Uout must not
- *            alias Us.  Call in order s = 0, 1, 2 after fam_dt.
+ *            alias Us.  Call in order s = 0, 1, 2 after fam_dt.  With the limiter's
+ *            segment list, the s = 0 launch also re-cuts the list from its row
+ *            costs for the following launches, as a step does.
  * fam_oe:    Uout = OE(Un) with the time step in dt_dev (Uout must not alias Un). */
 fam_status fam_dt(fam_ctx* ctx, const double* U, double dt_fixed, double* dt_dev);
 fam_status fam_stage(fam_ctx* ctx, int s, const double* U0, const double* Us, double* Uout,

@@ -537,7 +537,8 @@ extern "C" fam_status fam_stage(fam_ctx* c, int s, const double* U0, const doubl
                                 const double* dt_dev) {
   if (!c || s < 0 || s > 2 || !U0 || !Us || !Uout || !dt_dev || Uout == Us) return FAM_ERR_ARG;
   if (c->ninst != 1) return FAM_ERR_STATE;
-  enqueue_stage(c, s, 0, U0, Us, Uout, dt_dev);
+  // as in a step, the segment list (limiter on) is re-cut after the stage-0 launch only
+  enqueue_stage(c, s, 0, U0, Us, Uout, dt_dev, s == 0);
   return hipGetLastError() == hipSuccess ? FAM_OK : FAM_ERR_DEVICE;
 }
 
