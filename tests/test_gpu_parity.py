@@ -4,7 +4,7 @@ Each test runs the library through its C ABI (ctypes binding) and the oracle on
 the same seeded input and compares every output value.  Bar: relative L-infinity
 error <= 1e-12 per component (max |U_gpu - U_ora| over cells and moments divided
 by max |U_ora average| of that component).  Sizes are ragged with respect to the
-62-column strips and the row tiles, and boundaries are periodic or transmissive.
+60-column strips and the row tiles, and boundaries are periodic or transmissive.
 """
 import math
 
