@@ -94,15 +94,15 @@ __device__ __forceinline__ double half_wave_min(double v) {
   return fmin(v, __shfl_xor(v, 16, 64));
 }
 
-// LDS staging of the limiter's exact test: up to 8 cells of a wave at a time
-#ifndef FAM_PP_CHUNK
-#define FAM_PP_CHUNK 8
-#endif
-constexpr int PP_CHUNK = FAM_PP_CHUNK;
+// LDS staging of the limiter's exact test: up to CHUNK cells of a wave at a time
+// (16; 8 at k = 6, whose kernels also keep their carried traces in LDS and must
+// still fit four blocks per CU)
+template <int K>
 struct PPStage {
-  double cf[PP_CHUNK][4 * 21 + 1];   // coefficients of the 4 components, eps
-  double th[PP_CHUNK][2];
-  int nwork;                         // cells of this tile that needed the exact test
+  static constexpr int CHUNK = K == 6 ? 8 : 16;
+  double cf[CHUNK][4 * ncoef2d(K) + 1];   // coefficients of the 4 components, eps
+  double th[CHUNK][2];
+  int nwork;                               // cells of this tile that needed the exact test
 };
 
 // Called by all 64 lanes of the wave (uniform control flow).  Each lane first
@@ -113,7 +113,7 @@ struct PPStage {
 // instructions instead of a divergent 32-point loop.
 template <int K, int NCF, int MD, class P>
 __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NCF], bool& bad, int lane,
-                                           PPStage& S) {
+                                           PPStage<K>& S) {
   constexpr int NC = P::NC;
   if constexpr (NC != 4) {
     return;
@@ -170,10 +170,10 @@ __device__ __forceinline__ void pp_limiter(const P& phys, double (&cf)[P::NC][NC
     const double kk = 2.0 / (g - 1.0);
     double th1 = 1.0, th2 = 1.0;
     while (todo) {
-      // the next (up to) PP_CHUNK cells
+      // the next (up to) CHUNK cells
       unsigned long long chunk = 0, rest = todo;
       int nchunk = 0;
-      while (rest && nchunk < PP_CHUNK) {
+      while (rest && nchunk < PPStage<K>::CHUNK) {
         chunk |= rest & (~rest + 1ull);
         rest &= rest - 1ull;
         ++nchunk;
@@ -263,7 +263,7 @@ struct StageCarry<false> {
 };
 template <int K, class P, bool PP, bool DMR = false, bool CHAR = false>
 __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, int i0, int j0, int H,
-                           Window& W, PPStage& PS, StageCarry<carry_in_lds<K, P::NC>()>& T, double& amax_x,
+                           Window& W, PPStage<K>& PS, StageCarry<carry_in_lds<K, P::NC>()>& T, double& amax_x,
                            double& amax_y, bool& bad) {
   constexpr int NC = P::NC;
   constexpr int NCF = ncoef2d(K);
@@ -762,7 +762,7 @@ __device__ __forceinline__ int heavy_first_slot(int L, int N, int nh) {
 template <int K, class P, bool PP, bool DMR, bool CHAR = false>
 __global__ void FAM_STAGE_ATTR stage2d_kernel(StageArgs A, Inst in, int H) {
   __shared__ Window W;
-  __shared__ PPStage PS;
+  __shared__ PPStage<K> PS;
   __shared__ StageCarry<carry_in_lds<K, P::NC>()> T;
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
@@ -833,7 +833,7 @@ template <int K, class P, bool DMR, bool CHAR = false>
 __global__ void FAM_STAGE_ATTR stage2d_list_kernel(StageArgs A, Inst in, const int4* __restrict__ seg,
                                                     const int* __restrict__ nseg) {
   __shared__ Window W;
-  __shared__ PPStage PS;
+  __shared__ PPStage<K> PS;
   __shared__ StageCarry<carry_in_lds<K, P::NC>()> T;
   if (*A.done) return;
   const int n = *nseg;
@@ -1018,7 +1018,7 @@ template <int K, class P, bool PP>
 __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* __restrict__ insts,
                                                                 const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
-  __shared__ PPStage PS;
+  __shared__ PPStage<K> PS;
   __shared__ StageCarry<carry_in_lds<K, P::NC>()> T;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
