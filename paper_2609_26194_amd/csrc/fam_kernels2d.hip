@@ -47,7 +47,8 @@ namespace fam {
 #define FAM_OE_ATTR __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FAM_OE_WAVES)))
 
 // keeps the scheduler from hoisting the next component's LDS reads above this
-// point (bounds the number of live stencil values)
+// point (bounds the number of live stencil values); used between the OE kernel's
+// per-component passes (the stage kernels schedule faster without it)
 #ifndef FAM_NO_FENCE
 #define FAM_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 #else
@@ -361,7 +362,6 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
         coeffs2d<K>(u0, u1, u2, tmp, false);
 #pragma unroll
         for (int l = 0; l < NCF; ++l) cf[w][l] = tmp[l];
-        FAM_SCHED_FENCE();
       }
 #pragma unroll
       for (int l = 0; l < NCF; ++l) {
@@ -385,7 +385,6 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
         coeffs2d<K>(u0, u1, u2, tmp, false);
 #pragma unroll
         for (int l = 0; l < NCF; ++l) cf[c][l] = tmp[l];
-        FAM_SCHED_FENCE();
       }
     }
 
