@@ -426,13 +426,14 @@ fam_status set_stage_H(fam_ctx* c, int H) {
 }
 
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
-                          const double* dt_override, bool repartition) {
+                   const double* dt_override, bool repartition, double* Uout_mom) {
   static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
   fam::StageArgs A{};
   A.phys = c->phys;
   A.Us = Us;
   A.U0 = U0;
   A.Uout = Uout;
+  A.Uout_mom = Uout_mom;
   A.ca = CA[s];
   A.flag = c->flag;
   A.done = &c->st[0].done;
@@ -461,11 +462,13 @@ void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double
 }
 
 void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override,
-                double* delta_out) {
+                double* delta_out, const double* Ua) {
   fam::OEArgs A{};
   A.delta_out = delta_out;
   A.phys = c->phys;
   A.Un = Un;
+  A.Ua = Ua;
+  A.avg_in_place = Ua != nullptr && Ua == Uout;
   A.Uout = Uout;
   A.gamma_k = c->gamma_k;
   A.type = c->oe;
@@ -494,7 +497,14 @@ void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_f
   enqueue_stage(c, 1, parity, U, c->W1, c->W2, nullptr, false);
   if (c->oe == FAM_OE_OFF) {
     enqueue_stage(c, 2, parity, U, c->W2, U, nullptr, false);
+  } else if (c->dim == 2 && c->oe == FAM_OE_TYPE2) {
+    // the last stage writes its averages into U in place (each output cell reads
+    // only its own U0 value) and its moments into W1; the OE, which changes no
+    // average, reads both and writes only U's moment planes
+    enqueue_stage(c, 2, parity, U, c->W2, U, nullptr, false, c->W1);
+    enqueue_oe(c, parity, c->W1, U, nullptr, nullptr, U);
   } else {
+    // Type I's global statistics read one whole state: the OE input stays in W1
     enqueue_stage(c, 2, parity, U, c->W2, c->W1, nullptr, false);
     enqueue_oe(c, parity, c->W1, U, nullptr);
   }

@@ -80,8 +80,10 @@ fam_status reset_steps(fam_ctx* c, double t_final, double dt_fixed);
 fam_status save_clock(fam_ctx* c, std::vector<double>* t);
 fam_status restore_clock(fam_ctx* c, const std::vector<double>& t);
 void enqueue_alpha_full(fam_ctx* c, const double* U, int parity);
+// Uout_mom: moment planes of the output (NULL: Uout's own)
 void enqueue_stage(fam_ctx* c, int s, int parity, const double* U0, const double* Us, double* Uout,
-                   const double* dt_override, bool repartition = true);
+                   const double* dt_override, bool repartition = true, double* Uout_mom = nullptr);
+// Ua: average planes of the input (NULL: Un's own); when Ua == Uout they are left unwritten
 void enqueue_oe(fam_ctx* c, int parity, const double* Un, double* Uout, const double* dt_override,
-                double* delta_out = nullptr);
+                double* delta_out = nullptr, const double* Ua = nullptr);
 void enqueue_step(fam_ctx* c, double* U, int parity, double dt_fixed, double t_final);

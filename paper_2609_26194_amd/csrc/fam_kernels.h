@@ -47,6 +47,11 @@ struct StageArgs {
   const double* Us;
   const double* U0;
   double* Uout;
+  // moment planes (m = 1, 2) of the output; NULL: those of Uout.  With Uout the
+  // state and Uout_mom a stage buffer, the last stage of a step writes its
+  // averages in place (each output cell reads only its own U0 value) and leaves
+  // its moments for the OE, which then writes only moment planes
+  double* Uout_mom;
   // Shu-Osher stage ca U0 + (1 - ca) L with L = Us + dt R(Us), evaluated as
   // L + ca (U0 - L): the rounded 1/3 and 2/3 of the last stage sum to 1 - 2^-54,
   // which as separate weights would shrink every value by that much each step
@@ -67,6 +72,11 @@ struct StageArgs {
 struct OEArgs {
   PhysParams phys;
   const double* Un;
+  // average planes (m = 0) of the input; NULL: those of Un.  When they are
+  // Uout's own (avg_in_place = 1) the OE leaves them unwritten: it changes no
+  // average, so it then moves 8 planes per cell to HBM instead of 12
+  const double* Ua;
+  int avg_in_place;
   double* Uout;
   double gamma_k;
   int type;                // 1 or 2

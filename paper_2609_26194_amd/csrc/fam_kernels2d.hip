@@ -284,6 +284,8 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   const double* __restrict__ Us = A.Us + in.offset;
   const double* __restrict__ U0 = A.U0 + in.offset;
   double* __restrict__ Uo = A.Uout + in.offset;
+  // moment planes of the output, as an element offset from Uout (0: Uout's own)
+  const long long mom_off = A.Uout_mom ? (long long)(A.Uout_mom - A.Uout) : 0;
 
   double reg[NPLU];
 #pragma unroll 1
@@ -433,7 +435,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
         for (int m = 0; m < 3; ++m) {
           const double L = W.v[sl][c * 3 + m][col] + dt * Rm[m];
           const double v = use_u0 ? fma(A.ca, u0row[c * 3 + m] - L, L) : L;
-          Uo[(c * 3 + m) * in.plane + idx] = v;
+          Uo[(c * 3 + m) * in.plane + idx + (m == 0 ? 0 : mom_off)] = v;
           if (m == 0) avg[c] = v;
         }
       }
@@ -566,7 +568,7 @@ __device__ __forceinline__ void centre_values(const Window& W, int c, int col, i
 
 template <int K, class P, bool FULL, bool DMR = false>
 __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, int j0, int H,
-                        Window& W, bool& bad) {
+                        Window& W, double (&t1s)[8], bool& bad) {
   constexpr int NC = P::NC;
   constexpr int NPLU = NC * 3;
   const int lane = threadIdx.x;
@@ -577,20 +579,31 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   const double dt = *in.dt;
   const double tb = DMR ? *in.t_end : 0.0;   // OE: the end of the step
   const double cx = dt / in.dx, cy = dt / in.dy;
-  const double* __restrict__ Un = A.Un + in.offset;
+  // averages from Ua (NULL: Un), moments from Un, as an element offset from Ua
+  const double* __restrict__ Ua = (A.Ua ? A.Ua : A.Un) + in.offset;
+  const long long moff = A.Ua ? (long long)(A.Un - A.Ua) : 0;
   double* __restrict__ Uo = A.Uout + in.offset;
+  const bool write_avg = !A.avg_in_place;
+
+  // Type I: the instance's D_Omega and eps_Omega per component, read once into
+  // LDS (a global load inside the row loop would make the compiler wait there
+  // for every load in flight, the prefetched rows included, on either type)
+  if (A.type != 2 && lane < 2 * NC) {
+    const int q = lane < NC ? lane : 4 + lane - NC;   // D_Omega at 0..NC-1, eps_Omega at 4..3+NC
+    t1s[q] = A.stats[in.id * 8 + q];
+  }
 
   double reg[NPLU];
 #pragma unroll 1
   for (int r = j0 - 2; r <= j0; ++r) {
-    fetch_row<NPLU, DMR>(Un, in, i0, r, lane, reg, tb);
+    fetch_row<NPLU, DMR>(Ua, in, i0, r, lane, reg, tb, moff);
     store_row<NPLU>(W, slot_of(r), lane, reg);
   }
   __syncthreads();
   // rows are fetched two iterations ahead of their store into the window: ra holds
   // row r + 2 during iteration r, rb receives row r + 3
   double ra[NPLU], rb[NPLU];
-  if (j0 + 1 <= rend + 1) fetch_row<NPLU, DMR>(Un, in, i0, j0 + 1, lane, ra, tb);
+  if (j0 + 1 <= rend + 1) fetch_row<NPLU, DMR>(Ua, in, i0, j0 + 1, lane, ra, tb, moff);
 
   double prevTopC[NC];     // face-centre value at the top of the row below
   double prevJb[NC];       // |jump| at the bottom face of the row below
@@ -615,7 +628,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   for (int r = j0 - 1; r <= rend; ++r) {
     const bool pre = (r + 2 <= rend + 1);
     const bool pre2 = (r + 3 <= rend + 1);
-    if (pre2) fetch_row<NPLU, DMR>(Un, in, i0, r + 3, lane, rb, tb);
+    if (pre2) fetch_row<NPLU, DMR>(Ua, in, i0, r + 3, lane, rb, tb, moff);
     const int sl = slot_of(r - 1), sm = slot_of(r), sh = slot_of(r + 1);
     const bool ring_lo = (r == j0 - 1);
 
@@ -656,8 +669,8 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
             pD[c] = fmax(M - S, S - mn);
             pEps[c] = 1e-14 * fmax(fmax(fabs(M), fabs(mn)), 1.0);
           } else {
-            pD[c] = A.stats[in.id * 8 + c];       // D_Omega
-            pEps[c] = A.stats[in.id * 8 + 4 + c]; // eps_Omega
+            pD[c] = t1s[c];        // D_Omega
+            pEps[c] = t1s[4 + c];  // eps_Omega
           }
         }
       }
@@ -671,7 +684,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
       if (A.delta_out) A.delta_out[idx] = delta;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        Uo[(c * 3 + 0) * in.plane + idx] = W.v[sl][c * 3 + 0][col];
+        if (write_avg) Uo[(c * 3 + 0) * in.plane + idx] = W.v[sl][c * 3 + 0][col];
         Uo[(c * 3 + 1) * in.plane + idx] = W.v[sl][c * 3 + 1][col] * delta;
         Uo[(c * 3 + 2) * in.plane + idx] = W.v[sl][c * 3 + 2][col] * delta;
       }
@@ -1046,15 +1059,16 @@ __global__ void FAM_STAGE_ATTR stage2d_batched_kernel(StageArgs A, const Inst* _
 template <int K, class P, bool DMR>
 __global__ void FAM_OE_ATTR oe2d_kernel(OEArgs A, Inst in, int H) {
   __shared__ Window W;
+  __shared__ double t1s[8];
   if (*A.done) return;
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
   const int T = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int i0 = (T % gridDim.x) * STRIP, j0 = (T / gridDim.x) * H;
   if (K == 6 && A.k6_table)
-    oe_tile<K, P, true, DMR>(phys, A, in, i0, j0, H, W, bad);
+    oe_tile<K, P, true, DMR>(phys, A, in, i0, j0, H, W, t1s, bad);
   else
-    oe_tile<K, P, false, DMR>(phys, A, in, i0, j0, H, W, bad);
+    oe_tile<K, P, false, DMR>(phys, A, in, i0, j0, H, W, t1s, bad);
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }
 
@@ -1062,6 +1076,7 @@ template <int K, class P>
 __global__ void FAM_OE_ATTR oe2d_batched_kernel(OEArgs A, const Inst* __restrict__ insts,
                                                              const int4* __restrict__ work, int nwork) {
   __shared__ Window W;
+  __shared__ double t1s[8];
   const P phys = make_phys<P>(A.phys);
   bool bad = false;
   const bool one_each = (int)gridDim.x == nwork;   // then the XCD-aware order
@@ -1071,9 +1086,9 @@ __global__ void FAM_OE_ATTR oe2d_batched_kernel(OEArgs A, const Inst* __restrict
     const Inst in = insts[it.x];
     if (in.done && *in.done) continue;
     if (K == 6 && A.k6_table)
-      oe_tile<K, P, true>(phys, A, in, it.y, it.z, it.w, W, bad);
+      oe_tile<K, P, true>(phys, A, in, it.y, it.z, it.w, W, t1s, bad);
     else
-      oe_tile<K, P, false>(phys, A, in, it.y, it.z, it.w, W, bad);
+      oe_tile<K, P, false>(phys, A, in, it.y, it.z, it.w, W, t1s, bad);
   }
   if (__any(bad) && threadIdx.x == 0) atomicOr(A.flag, 1);
 }

@@ -27,7 +27,7 @@ __device__ __forceinline__ int slot_of(int r) { return ((r % 3) + 3) % 3; }
 // outside the mesh) at boundary time tb; see fam_config.dmr
 template <int NPLU>
 __device__ __forceinline__ void dmr_ghost(const double* __restrict__ U, const Inst& in, int r, int ci, double tb,
-                                          double (&reg)[NPLU]) {
+                                          double (&reg)[NPLU], long long moff) {
   const double xc = in.x0 + (ci + 0.5) * in.dx;
   int which = -1;   // 0: post-shock state, 1: pre-shock state, -1: copy or mirror
   if (r >= in.ny)   // top: the exact shock line at the upper boundary
@@ -52,21 +52,23 @@ __device__ __forceinline__ void dmr_ghost(const double* __restrict__ U, const In
   const size_t base = (size_t)gj * in.nx + gi;
 #pragma unroll
   for (int p = 0; p < NPLU; ++p) {
-    const double v = U[p * in.plane + base];
+    const double v = U[p * in.plane + base + (p % 3 == 0 ? 0 : moff)];
     const bool neg = r < 0 && ((p / 3 == 2) ? (p % 3 != 2) : (p % 3 == 2));
     reg[p] = neg ? -v : v;
   }
 }
 
-// DMR: the instance uses the double Mach reflection boundaries (a separate
-// instantiation, so the plain kernels carry none of its registers)
+// Row r of the state U; its moment planes (m = 1, 2) lie moff elements after
+// the places U's own would have (0: a plain state).  DMR: the instance uses the
+// double Mach reflection boundaries (a separate instantiation, so the plain
+// kernels carry none of its registers)
 template <int NPLU, bool DMR>
 __device__ __forceinline__ void fetch_row(const double* __restrict__ U, const Inst& in, int i0, int r,
-                                          int lane, double (&reg)[NPLU], double tb) {
+                                          int lane, double (&reg)[NPLU], double tb, long long moff = 0) {
   const int ci = i0 - 2 + lane;
   if constexpr (DMR) {
     if (r < 0 || r >= in.ny || ci < 0 || ci >= in.nx) {
-      dmr_ghost<NPLU>(U, in, r, ci, tb, reg);
+      dmr_ghost<NPLU>(U, in, r, ci, tb, reg, moff);
       return;
     }
   }
@@ -74,7 +76,7 @@ __device__ __forceinline__ void fetch_row(const double* __restrict__ U, const In
   const int gi = ghost(ci, in.nx, in.bcx);
   const size_t base = (size_t)gj * in.nx + gi;
 #pragma unroll
-  for (int p = 0; p < NPLU; ++p) reg[p] = U[p * in.plane + base];
+  for (int p = 0; p < NPLU; ++p) reg[p] = U[p * in.plane + base + (p % 3 == 0 ? 0 : moff)];
 }
 
 template <int NPLU>
