@@ -159,12 +159,13 @@ extern "C" fam_status fam_step_static(const fam_config* cfg, void* hip_stream, d
   fam::launch_step_begin(st, 1, 0, dt_fixed, 0.0, s);
 
   static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
-  auto stage = [&](int k_s, const double* Us, double* Uout) {
+  auto stage = [&](int k_s, const double* Us, double* Uout, double* Uout_mom) {
     fam::StageArgs A{};
     A.phys = phys;
     A.Us = Us;
     A.U0 = U;
     A.Uout = Uout;
+    A.Uout_mom = Uout_mom;
     A.ca = CA[k_s];
     A.flag = flag;
     A.done = &st->done;
@@ -181,16 +182,24 @@ extern "C" fam_status fam_step_static(const fam_config* cfg, void* hip_stream, d
     else
       fam::launch_stage2d(f.k, f.system, A, is, H, s);
   };
-  stage(0, U, W1);
-  stage(1, W1, W2);
+  stage(0, U, W1, nullptr);
+  stage(1, W1, W2, nullptr);
   if (f.oe == FAM_OE_OFF) {
-    stage(2, W2, U);
+    stage(2, W2, U, nullptr);
   } else {
-    stage(2, W2, W1);
+    // as in fam_step: with Type II in 2D the last stage writes its averages into U
+    // in place and its moments into W1, and the OE writes only U's moment planes
+    const bool split = dim == 2 && f.oe == FAM_OE_TYPE2;
+    if (split)
+      stage(2, W2, U, W1);
+    else
+      stage(2, W2, W1, nullptr);
     fam::OEArgs A{};
     A.delta_out = nullptr;
     A.phys = phys;
     A.Un = W1;
+    A.Ua = split ? U : nullptr;
+    A.avg_in_place = split;
     A.Uout = U;
     A.gamma_k = f.oe_gamma_k > 0 ? f.oe_gamma_k : default_gamma_k(dim, f.k);
     A.type = f.oe;
