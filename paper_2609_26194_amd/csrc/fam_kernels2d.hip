@@ -285,7 +285,7 @@ __device__ void stage_tile(const P& phys, const StageArgs& A, const Inst& in, in
   const double* __restrict__ U0 = A.U0 + in.offset;
   double* __restrict__ Uo = A.Uout + in.offset;
   // moment planes of the output, as an element offset from Uout (0: Uout's own)
-  const long long mom_off = A.Uout_mom ? (long long)(A.Uout_mom - A.Uout) : 0;
+  const long long mom_off = A.Uout_mom ? elem_offset(A.Uout, A.Uout_mom) : 0;
 
   double reg[NPLU];
 #pragma unroll 1
@@ -581,7 +581,7 @@ __device__ void oe_tile(const P& phys, const OEArgs& A, const Inst& in, int i0, 
   const double cx = dt / in.dx, cy = dt / in.dy;
   // averages from Ua (NULL: Un), moments from Un, as an element offset from Ua
   const double* __restrict__ Ua = (A.Ua ? A.Ua : A.Un) + in.offset;
-  const long long moff = A.Ua ? (long long)(A.Un - A.Ua) : 0;
+  const long long moff = A.Ua ? elem_offset(A.Ua, A.Un) : 0;
   double* __restrict__ Uo = A.Uout + in.offset;
   const bool write_avg = !A.avg_in_place;
 

@@ -58,6 +58,13 @@ __device__ __forceinline__ void dmr_ghost(const double* __restrict__ U, const In
   }
 }
 
+// b - a in doubles for two arrays of doubles that may be separate allocations
+// (integer addresses: a pointer difference is defined only within one array;
+// both are 8-byte aligned, so the byte difference shifts exactly)
+__device__ __forceinline__ long long elem_offset(const double* a, const double* b) {
+  return ((long long)(uintptr_t)b - (long long)(uintptr_t)a) >> 3;
+}
+
 // Row r of the state U; its moment planes (m = 1, 2) lie moff elements after
 // the places U's own would have (0: a plain state).  DMR: the instance uses the
 // double Mach reflection boundaries (a separate instantiation, so the plain
