@@ -255,6 +255,38 @@ def stage_roofline(fam, U, k, cells, seg_list, reps=10):
             "hbm_algorithmic_GBs": gbs, "hbm_algorithmic_frac": gbs / HBM_PEAK_GBS}
 
 
+def oe_roofline(fam, U, k, cells, reps=10):
+    """The OE kernel's launch through fam_oe (which writes all 12 planes: 192 B per cell; the
+    step's own OE writes the 8 moment planes, 160 B), on the pre-OE state of one step from U,
+    HIP events on the library stream."""
+    import torch
+    from paper_2609_26194_amd.fam import fam_oe, fam_stage
+    from paper_2609_26194_amd.opcount import oe_flops
+    dtd = fam.dt(U)
+    W1, W2, W3 = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
+    fam_stage(fam.h, 0, U, U, W1, dtd)
+    fam_stage(fam.h, 1, U, W1, W2, dtd)
+    fam_stage(fam.h, 2, U, W2, W3, dtd)
+    durs = []
+    for rep in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fam.stream.wait_stream(torch.cuda.current_stream())
+        e0.record(fam.stream)
+        fam_oe(fam.h, W3, W1, dtd)
+        e1.record(fam.stream)
+        torch.cuda.current_stream().wait_stream(fam.stream)
+        e1.synchronize()
+        if rep > 0:
+            durs.append(e0.elapsed_time(e1) * 1e-3)
+    dur = sum(durs) / len(durs)
+    bytes_alg = 24 * 8 * cells
+    gbs = bytes_alg / dur / 1e9
+    return {"kernel": f"oe2d_kernel<{k}, Euler<2>> through fam_oe (12 planes written)", "bound": "hbm",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "launch_ms": dur * 1e3, "algorithmic_bytes_per_launch": bytes_alg,
+            "flops_per_cell": oe_flops(k)}
+
+
 def copy_calibration():
     """One plain streaming kernel that reads COPY_BYTES and writes COPY_BYTES (y = 1.0 * x),
     the HBM-counter calibration.  The buffers exceed the 256 MB last-level cache and a
@@ -535,6 +567,8 @@ def main_workload(args, n, k):
     value = cells * steps / elapsed
     log("stage launches")
     roofline = stage_roofline(fam, U, k, cells, seg_list=tuned[0] == 0)
+    log("OE launches")
+    oe_roof = oe_roofline(fam, U, k, cells)
     fam.close()
     copy_calibration()
     # the whole step's algorithmic HBM rate: cell-updates/s x 928 B (three stages and the OE)
@@ -557,6 +591,7 @@ def main_workload(args, n, k):
                                f"transmissive, CFL 0.2, positivity limiter", "cells": cells, "k": k, "t_simulated": t_sim,
                    "autotuned_tile_heights": {"stage": tuned[0], "oe": tuned[1]}},
         "roofline": roofline,
+        "oe_roofline": oe_roof,
     }
 
 
