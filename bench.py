@@ -213,26 +213,39 @@ def cpu_baseline(n, steps):
                               "sample": f"{n1}x{n1} cells, {steps1} steps after one warm-up step ({dt1:.1f} s)"}}
 
 
+def timed_launches(fam, calls, reps):
+    """Back-to-back launches of calls (a list of (key, fn)) on the library stream, reps + 1
+    times, each bracketed by a HIP event pair on that stream; one host synchronisation at the
+    end, so the device stays busy as in a run.  Returns {key: [seconds per launch]} without
+    the first repetition."""
+    import torch
+    ev = []
+    fam.stream.wait_stream(torch.cuda.current_stream())
+    for rep in range(reps + 1):
+        for key, fn in calls:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(fam.stream)
+            fn()
+            e1.record(fam.stream)
+            ev.append((rep, key, e0, e1))
+    torch.cuda.current_stream().wait_stream(fam.stream)
+    ev[-1][3].synchronize()
+    out = {}
+    for rep, key, e0, e1 in ev:
+        if rep > 0:
+            out.setdefault(key, []).append(e0.elapsed_time(e1) * 1e-3)
+    return out
+
+
 def stage_roofline(fam, U, k, cells, seg_list, reps=10):
     """Per-launch duration of the three RK stage launches, HIP events on the library stream."""
     import torch
     from paper_2609_26194_amd.fam import fam_stage
     dtd = fam.dt(U)
     W1, W2 = torch.empty_like(U), torch.empty_like(U)
-    ins = {0: (U, U, W1), 1: (U, W1, W2), 2: (U, W2, W1)}
-    durs = {0: [], 1: [], 2: []}
-    for rep in range(reps + 1):
-        for s in range(3):
-            U0_, Us_, Uo_ = ins[s]
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            fam.stream.wait_stream(torch.cuda.current_stream())
-            e0.record(fam.stream)
-            fam_stage(fam.h, s, U0_, Us_, Uo_, dtd)
-            e1.record(fam.stream)
-            torch.cuda.current_stream().wait_stream(fam.stream)
-            e1.synchronize()
-            if rep > 0:
-                durs[s].append(e0.elapsed_time(e1) * 1e-3)
+    calls = [(0, lambda: fam_stage(fam.h, 0, U, U, W1, dtd)), (1, lambda: fam_stage(fam.h, 1, U, W1, W2, dtd)),
+             (2, lambda: fam_stage(fam.h, 2, U, W2, W1, dtd))]
+    durs = timed_launches(fam, calls, reps)
     avg = {s: sum(v) / len(v) for s, v in durs.items()}
     dur = sum(avg.values()) / 3.0
     from paper_2609_26194_amd.opcount import stage_flops
@@ -267,17 +280,7 @@ def oe_roofline(fam, U, k, cells, reps=10):
     fam_stage(fam.h, 0, U, U, W1, dtd)
     fam_stage(fam.h, 1, U, W1, W2, dtd)
     fam_stage(fam.h, 2, U, W2, W3, dtd)
-    durs = []
-    for rep in range(reps + 1):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fam.stream.wait_stream(torch.cuda.current_stream())
-        e0.record(fam.stream)
-        fam_oe(fam.h, W3, W1, dtd)
-        e1.record(fam.stream)
-        torch.cuda.current_stream().wait_stream(fam.stream)
-        e1.synchronize()
-        if rep > 0:
-            durs.append(e0.elapsed_time(e1) * 1e-3)
+    durs = timed_launches(fam, [("oe", lambda: fam_oe(fam.h, W3, W1, dtd))], reps)["oe"]
     dur = sum(durs) / len(durs)
     bytes_alg = 24 * 8 * cells
     gbs = bytes_alg / dur / 1e9
@@ -440,18 +443,9 @@ def launch_split(fam, U, reps=10):
     W1, W2, W3 = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
     calls = [("stage", lambda: fam_stage(fam.h, 0, U, U, W1, dtd)), ("stage", lambda: fam_stage(fam.h, 1, U, W1, W2, dtd)),
              ("stage", lambda: fam_stage(fam.h, 2, U, W2, W3, dtd)), ("oe", lambda: fam_oe(fam.h, W3, W1, dtd))]
-    tot = {"stage": 0.0, "oe": 0.0}
-    for rep in range(reps + 1):
-        for name, fn in calls:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            fam.stream.wait_stream(torch.cuda.current_stream())
-            e0.record(fam.stream)
-            fn()
-            e1.record(fam.stream)
-            e1.synchronize()
-            if rep:
-                tot[name] += e0.elapsed_time(e1) / reps
-    return tot
+    durs = timed_launches(fam, calls, reps)
+    # per step: the three stage launches summed, the OE launch (ms)
+    return {"stage": sum(durs["stage"]) / reps * 1e3, "oe": sum(durs["oe"]) / reps * 1e3}
 
 
 def char_leg(so_n=4000, so_steps=2000, dmr_steps=1000):
