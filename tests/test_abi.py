@@ -97,7 +97,7 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(fam, "LIB_PATH", str(tmp_path / "libfam.so"))
     with pytest.raises(RuntimeError, match="missing"):
         fam.load_library()
-    # the context raises too (here first for the missing device, on a GPU machine for the library)
+    # the context raises too (here first for the missing device, on a machine with a GPU for the library)
     with pytest.raises(RuntimeError):
         fam.Fam(fam.FamConfig(dim=2, nx=8, ny=8))
 
